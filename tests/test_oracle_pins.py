@@ -1,0 +1,415 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside it: exact lattice
+identities, moment identities of the equilibrium, conservation laws, closed
+forms (plane Poiseuille, Hagen-Poiseuille, Womersley), symmetry, a dense
+brute-force lattice, and the numbers printed in the paper for Eq. (2).
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term,
+a wrong sign or index, a swapped branch) makes it fail.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# lattice and equilibrium
+# --------------------------------------------------------------------------
+def test_lattice_constants(oracle_mod):
+    c, w = oracle_mod.lattice()
+    assert np.array_equal(c, synth.DIRS), "oracle velocity order differs from the site-list interface"
+    # weights are exact rationals k/36; check the moment identities in integers
+    W36 = np.rint(w * 36).astype(np.int64)
+    assert np.all(w == W36 / 36.0)
+    d = np.eye(3, dtype=np.int64)
+    cc = c.astype(np.int64)
+    assert W36.sum() == 36
+    assert not np.einsum("i,ia->a", W36, cc).any()
+    assert np.array_equal(np.einsum("i,ia,ib->ab", W36, cc, cc), 12 * d)
+    assert not np.einsum("i,ia,ib,ic->abc", W36, cc, cc, cc).any()
+    iso4 = np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) + np.einsum("ad,bc->abcd", d, d)
+    assert np.array_equal(np.einsum("i,ia,ib,ic,id->abcd", W36, cc, cc, cc, cc), 4 * iso4)
+    for i in range(1, 19):
+        ib = i + 1 if i % 2 else i - 1
+        assert np.array_equal(c[ib], -c[i])
+        assert w[ib] == w[i]
+
+
+def _rand_state(rng):
+    rho = rng.uniform(0.9, 1.1)
+    u = rng.uniform(-0.08, 0.08, 3)
+    return rho, u
+
+
+def test_feq_moments(oracle_mod):
+    """sum feq = rho, sum c feq = rho u, sum c c feq = rho/3 I + rho u u."""
+    c, _ = oracle_mod.lattice()
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        rho, u = _rand_state(rng)
+        fe = oracle_mod.feq(rho, u)
+        assert abs(fe.sum() - rho) < 1e-15
+        assert np.abs(c.T @ fe - rho * u).max() < 1e-15
+        P = np.einsum("i,ia,ib->ab", fe, c, c)
+        assert np.abs(P - (rho / 3 * np.eye(3) + rho * np.outer(u, u))).max() < 2e-15
+
+
+def test_feq_cube_covariance(oracle_mod):
+    """feq_{g(i)}(rho, g u) = feq_i(rho, u) for every signed permutation g."""
+    c, _ = oracle_mod.lattice()
+    rng = np.random.default_rng(2)
+    rho, u = _rand_state(rng)
+    base = oracle_mod.feq(rho, u)
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            G = np.zeros((3, 3))
+            for a in range(3):
+                G[a, perm[a]] = signs[a]
+            gc = c @ G.T
+            idx = [int(np.flatnonzero((c == gc[i]).all(1))[0]) for i in range(19)]
+            moved = oracle_mod.feq(rho, G @ u)
+            assert np.abs(moved[idx] - base).max() < 1e-16
+
+
+def test_collision_conserves_and_relaxes(oracle_mod):
+    """Mass is conserved, momentum gains exactly F (Guo), and the
+    non-equilibrium part shrinks by (1 - 1/tau) when F = 0."""
+    c, w = oracle_mod.lattice()
+    rng = np.random.default_rng(3)
+    for tau in (0.51, 0.8, 1.0, 1.7):
+        for _ in range(10):
+            rho, u = _rand_state(rng)
+            f = oracle_mod.feq(rho, u) + rng.normal(0, 1e-3, 19) * w
+            F = rng.normal(0, 1e-4, 3)
+            fs = oracle_mod.collide_site(f, tau, F)
+            assert abs(fs.sum() - f.sum()) < 1e-15
+            assert np.abs(c.T @ fs - (c.T @ f + F)).max() < 1e-16
+            fs0 = oracle_mod.collide_site(f, tau)
+            r, u0 = oracle_mod.moments_site(f)
+            fe = oracle_mod.feq(r, u0)
+            assert np.abs((fs0 - fe) - (1 - 1 / tau) * (f - fe)).max() < 1e-16
+
+
+# --------------------------------------------------------------------------
+# small systems
+# --------------------------------------------------------------------------
+def _system(oracle_mod, geo, tau=0.8, mode=None, u_in=0.0, rho_out=1.0, F=None, omega=0.0):
+    s = oracle_mod.System(1)
+    s.set_geometry(0, geo)
+    s.set_params(0, tau, oracle_mod.SBB if mode is None else mode)
+    for k, io in enumerate(geo.iolets):
+        if io.kind == "inlet":
+            s.set_iolet(0, k, oracle_mod.INLET, io.centre, io.normal, io.radius, a0=u_in)
+        else:
+            s.set_iolet(0, k, oracle_mod.OUTLET, io.centre, io.normal, io.radius, a0=rho_out)
+    if F is not None:
+        s.set_force(0, F, omega)
+    s.init()
+    return s
+
+
+@pytest.mark.parametrize("mode", ["sbb", "bouzidi"])
+def test_rest_state_is_fixed_point(oracle_mod, mode):
+    geo = synth.cylinder(q="random", seed=5) if mode == "bouzidi" else synth.cylinder()
+    s = _system(oracle_mod, geo, mode=oracle_mod.BOUZIDI if mode == "bouzidi" else oracle_mod.SBB)
+    s.step(50)
+    _, w = oracle_mod.lattice()
+    assert np.abs(s.f() - w[:, None]).max() < 5e-16
+
+
+def _neumaier(a):
+    s = 0.0
+    comp = 0.0
+    for v in a:
+        t = s + v
+        if abs(s) >= abs(v):
+            comp += (s - t) + v
+        else:
+            comp += (v - t) + s
+        s = t
+    return s + comp
+
+
+def test_mass_conserved_in_closed_domains(oracle_mod):
+    """Bounce-back walls and periodic wrap conserve the total mass exactly
+    (to round-off) while a body force drives flow."""
+    for ends in ("periodic", "closed"):
+        geo = synth.cylinder(nz=16, ends=ends)
+        s = _system(oracle_mod, geo, tau=0.7, F=(1e-5, 0.0, 2e-5))
+        m0 = _neumaier(s.f().ravel())
+        s.step(400)
+        m1 = _neumaier(s.f().ravel())
+        assert abs(m1 - m0) / m0 < 1e-13
+        _, u = s.moments()
+        if ends == "periodic":          # the closed tube settles to hydrostatic balance
+            assert np.abs(u[2]).max() > 1e-3
+
+
+def _dense_reference(solid, F, tau, steps):
+    """Dense lattice on a periodic box with np.roll streaming and halfway
+    bounce-back at solid cells.  Written here independently of the oracle."""
+    c = synth.DIRS
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    fluid = ~solid
+    f = np.broadcast_to(w[:, None, None, None], (19,) + solid.shape).copy()
+    Fv = np.asarray(F, float)
+    H = np.einsum("ia,ib->iab", c, c) - np.eye(3) / 3.0      # second Hermite tensor
+    for _ in range(steps):
+        rho = f.sum(0)
+        mom = np.einsum("ia,izyx->azyx", c, f)
+        u = (mom + 0.5 * Fv[:, None, None, None]) / rho
+        # equilibrium written as its Hermite expansion: w rho (1 + 3 c.u + 9/2 H:uu)
+        cu = np.einsum("ia,azyx->izyx", c, u)
+        Huu = np.einsum("iab,azyx,bzyx->izyx", H, u, u)
+        feq = w[:, None, None, None] * rho * (1 + 3 * cu + 4.5 * Huu)
+        # Guo source written as w (1 - 1/2tau) [3 c.F + 9 H:(u F)]
+        cF = c @ Fv
+        HuF = np.einsum("iab,azyx,b->izyx", H, u, Fv)
+        src = (1 - 0.5 / tau) * w[:, None, None, None] * (3 * cF[:, None, None, None] + 9 * HuF)
+        fs = f + (feq - f) / tau + src
+        fn = np.empty_like(fs)
+        for i in range(19):
+            fn[i] = np.roll(fs[i], shift=(c[i, 2], c[i, 1], c[i, 0]), axis=(0, 1, 2))
+        for i in range(1, 19):
+            ib = i + 1 if i % 2 else i - 1
+            hits = fluid & np.roll(solid, shift=(-c[i, 2], -c[i, 1], -c[i, 0]), axis=(0, 1, 2))
+            fn[ib][hits] = fs[i][hits]
+        f = fn
+    return f
+
+
+def test_sparse_addressing_matches_dense_bruteforce(oracle_mod):
+    nx, ny, nz = 9, 7, 6
+    gz, gy, gx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    solid = (gx - 4.2) ** 2 + (gy - 3.1) ** 2 + (gz - 2.7) ** 2 < 5.0
+    solid |= (gy == 0)
+    geo = synth.box(nx, ny, nz, periodic=(True, True, True), solid=solid)
+    F = (2e-4, -1e-4, 3e-4)
+    s = _system(oracle_mod, geo, tau=0.9, F=F)
+    s.step(30)
+    dense = _dense_reference(solid, F, 0.9, 30)
+    x, y, z = geo.coords
+    ref = dense[:, z, y, x]
+    assert np.abs(s.f() - ref).max() < 1e-15
+
+
+def test_cylinder_mirror_and_rotation_symmetry(oracle_mod):
+    geo = synth.cylinder(nz=24)
+    s = _system(oracle_mod, geo, u_in=0.01)
+    s.step(300)
+    rho, u = s.moments()
+    x, y, z = (v.astype(np.int64) for v in geo.coords)
+    key = {(a, b, cc): i for i, (a, b, cc) in enumerate(zip(x, y, z))}
+    mx = np.array([key[(19 - a, b, cc)] for a, b, cc in zip(x, y, z)])
+    scale = np.abs(u).max()
+    assert np.abs(u[0] + u[0, mx]).max() / scale < 1e-13
+    assert np.abs(u[1:] - u[1:, mx]).max() / scale < 1e-13
+    assert np.abs(rho - rho[mx]).max() < 1e-13
+    rot = np.array([key[(19 - b, a, cc)] for a, b, cc in zip(x, y, z)])   # (x,y) -> (19-y, x)
+    # rotating the field by 90 degrees about the axis: u'(R p) = R u(p)
+    assert np.abs(u[0, rot] - (-u[1])).max() / scale < 1e-13
+    assert np.abs(u[1, rot] - u[0]).max() / scale < 1e-13
+    assert np.abs(u[2, rot] - u[2]).max() / scale < 1e-13
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+def _channel_profile(oracle_mod, H, tau, F, steps, q=None, mode=None):
+    geo = synth.channel(nx=1, ny=H, nz=1)
+    if q is not None:
+        s_, d_ = geo.wall_links()
+        geo.q_site, geo.q_dir = s_, d_
+        geo.q = np.full(s_.size, q, np.float32)
+    s = _system(oracle_mod, geo, tau=tau, F=(F, 0.0, 0.0), mode=mode)
+    s.step(steps)
+    rho, u = s.moments()
+    return geo.coords[1].astype(float), u[0], rho, s
+
+
+def test_plane_poiseuille_exact_at_magic_tau(oracle_mod):
+    """Halfway bounce-back with BGK and Guo forcing gives the exact parabola
+    when (tau - 1/2)^2 = 3/16 (He, Zou, Luo & Dembo 1997; Ginzburg &
+    d'Humieres 2003); other tau show an O(1) slip."""
+    H, F = 8, 1e-6
+    tau = (2 + np.sqrt(3)) / 4
+    y, ux, rho, _ = _channel_profile(oracle_mod, H, tau, F, 3000)
+    nu = (tau - 0.5) / 3
+    exact = F / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
+    assert np.abs(ux - exact).max() / exact.max() < 1e-9
+    y, ux, _, _ = _channel_profile(oracle_mod, H, 0.8, F, 3000)
+    nu = 0.1
+    exact = F / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
+    assert np.abs(ux - exact).max() / exact.max() > 1e-3
+
+
+def test_wall_shear_stress_plane_poiseuille(oracle_mod):
+    """At the first fluid node the shear stress of the exact parabola is
+    F (H - 1) / 2 (the force balance of the channel, evaluated half a
+    spacing inside the wall)."""
+    H, F = 8, 1e-6
+    tau = (2 + np.sqrt(3)) / 4
+    y, _, _, s = _channel_profile(oracle_mod, H, tau, F, 3000)
+    wss = s.wss()
+    edge = (y == 0) | (y == H - 1)
+    assert np.all(wss[~edge] == 0)
+    assert np.abs(wss[edge] - F * (H - 1) / 2).max() / (F * (H - 1) / 2) < 1e-6
+
+
+def test_bouzidi_second_order_vs_bounce_back_first_order(oracle_mod):
+    """Walls a quarter spacing from the outer nodes: linear Bouzidi converges
+    at second order, halfway bounce-back (wall misplaced) at first order."""
+    tau, q = 0.8, 0.25
+    errs = {"bz": [], "sbb": []}
+    for H in (6, 12, 24):
+        width = (H - 1) + 2 * q
+        F = 1e-6 * (6.0 / width) ** 2
+        steps = int(25 * width ** 2 / ((tau - 0.5) / 3) / 10)
+        for key, mode in (("bz", oracle_mod.BOUZIDI), ("sbb", oracle_mod.SBB)):
+            y, ux, _, _ = _channel_profile(oracle_mod, H, tau, F, steps, q=q, mode=mode)
+            nu = (tau - 0.5) / 3
+            exact = F / (2 * nu) * (y + q) * (H - 1 + q - y)
+            errs[key].append(np.sqrt(np.mean((ux - exact) ** 2) / np.mean(exact ** 2)))
+    bz, sb = np.array(errs["bz"]), np.array(errs["sbb"])
+    order_bz = np.log2(bz[:-1] / bz[1:])
+    order_sb = np.log2(sb[:-1] / sb[1:])
+    assert np.all(order_bz > 1.7), (bz, order_bz)
+    assert np.all(order_sb < 1.3), (sb, order_sb)
+    assert bz[-1] < sb[-1] / 5
+
+
+@pytest.fixture(scope="module")
+def c1_steady(oracle_mod):
+    geo = synth.cylinder()
+    s = _system(oracle_mod, geo, tau=0.8, u_in=0.01)
+    s.step(1000)
+    return geo, s
+
+
+def test_hagen_poiseuille_c1(c1_steady):
+    """Cylinder, velocity inlet, pressure outlet, 1000 steps: the mid-length
+    profile is the parabola within the staircase error, the axial pressure
+    gradient matches G = 4 nu u_max / R^2, the outlet holds rho_out and the
+    flux is the same at inlet, middle and outlet."""
+    geo, s = c1_steady
+    rho, u = s.moments()
+    x, y, z = geo.coords
+    r2 = (x - 9.5) ** 2 + (y - 9.5) ** 2
+    mid = z == 32
+    fit = np.polyfit(r2[mid], u[2, mid], 1)
+    umax, R2 = fit[1], -fit[1] / fit[0]
+    assert abs(umax - 0.01) / 0.01 < 0.05
+    assert abs(np.sqrt(R2) - 8.0) < 0.6
+    prof = umax * (1 - r2[mid] / R2)
+    assert np.sqrt(np.mean((u[2, mid] - prof) ** 2)) / umax < 0.02
+    pz = np.array([rho[z == k].mean() / 3 for k in range(16, 49)])
+    G = -np.polyfit(np.arange(16, 49), pz, 1)[0]
+    assert abs(G - 4 * 0.1 * umax / R2) / G < 0.08
+    mu, mp, area = s.iolet_stats()
+    assert abs(mp[1]) < 1e-5
+    flux = [u[2, z == k].mean() for k in (0, 32, 63)]
+    assert np.ptp(flux) / np.mean(flux) < 0.03
+    assert area.tolist() == [208, 208]
+
+
+def test_womersley_pipe(oracle_mod):
+    """Periodic pipe driven by F = G0 cos(w t): after three periods the
+    profile follows Womersley's solution within the staircase error."""
+    from scipy.special import jv
+    R, tau, alpha = 8.0, 0.8, 4.0
+    nu = (tau - 0.5) / 3
+    omega = alpha ** 2 * nu / R ** 2
+    G0 = 1e-5
+    geo = synth.cylinder(nz=2, ends="periodic")
+    s = _system(oracle_mod, geo, tau=tau, F=(0.0, 0.0, G0), omega=omega)
+    period = 2 * np.pi / omega
+    x, y, z = geo.coords
+    r = np.sqrt((x - 9.5) ** 2 + (y - 9.5) ** 2)
+    Reff = R
+    i32 = np.exp(1j * 3 * np.pi / 4)
+    errs = []
+    n0 = int(3 * period)
+    s.step(n0)
+    for k in range(8):
+        t = s.t
+        _, u = s.moments()
+        ana = np.real(G0 / (1j * omega) * (1 - jv(0, i32 * alpha * r / Reff) / jv(0, i32 * alpha))
+                      * np.exp(1j * omega * t))
+        amp = np.abs(G0 / (1j * omega) * (1 - 1 / jv(0, i32 * alpha)))
+        errs.append(np.sqrt(np.mean((u[2] - ana) ** 2)) / amp)
+        s.step(int(period / 8))
+    assert max(errs) < 0.06, errs
+
+
+# --------------------------------------------------------------------------
+# Eq. (2) and the printed 1:3 example
+# --------------------------------------------------------------------------
+def test_velocity_factors_conserve_mass(oracle_mod):
+    rng = np.random.default_rng(11)
+    for nv in (1, 2, 3, 13):
+        dp = rng.uniform(0.3, 0.7, nv)
+        L = rng.uniform(5, 50, nv)
+        A = rng.uniform(10, 200, nv)
+        A0 = rng.uniform(50, 500)
+        v = oracle_mod.velocity_factors(dp, L, A, A0)
+        assert abs((A * v).sum() - A0) / A0 < 1e-14
+        if nv == 1:
+            assert abs(v[0] - A0 / A[0]) < 1e-14 * A0 / A[0]
+
+
+def test_velocity_factors_paper_example(oracle_mod):
+    """The 1:3 example of Sec. 3: equal areas, the printed pressure factors
+    and the printed velocity factors; the distances are not printed, so the
+    fixture holds the distance ratios they imply."""
+    with open(os.path.join(GOLDEN, "coupling_1to3.json")) as fh:
+        g = json.load(fh)
+    v = oracle_mod.velocity_factors(g["dP_over_P0"], g["L_ratio"], [1.0, 1.0, 1.0], 1.0)
+    assert np.abs(v - np.array(g["v_over_v0"])).max() <= g["print_tolerance"]
+    assert abs(v.sum() - 1.0) < 1e-15
+
+
+def _coupled_1to3(oracle_mod, mode, steps, u_in=0.01):
+    art = synth.tubes(1, radius=4.0, length=24)
+    ven = synth.tubes(3, radius=4.0, length=24)
+    dp = np.array([0.30, 0.52, 0.69])
+    A = np.full(3, 1.0)
+    s_fac = oracle_mod.velocity_factors(dp, [1.0, 0.6156, 0.5639], A, 1.0)
+    sys_ = oracle_mod.System(2)
+    for d, g in enumerate((art, ven)):
+        sys_.set_geometry(d, g)
+        sys_.set_params(d, 0.8)
+    io = art.iolets[0]
+    sys_.set_iolet(0, 0, oracle_mod.INLET, io.centre, io.normal, io.radius, a0=u_in)
+    for i in range(3):
+        sys_.couple(0, 1, 1, i, s_fac[i], dp[i])
+    sys_.set_coupling_mode(mode)
+    sys_.init()
+    sys_.step(steps)
+    return sys_, s_fac, dp
+
+
+@pytest.mark.parametrize("mode", ["alternate", "both"])
+def test_coupled_1to3_reaches_eq2_ratios(oracle_mod, mode):
+    """Sec. 3, 1:3 test: at steady state each venous inlet carries the Eq. (2)
+    share of the arterial outlet's mean velocity, total flux is conserved
+    across the coupling, and the arterial outlet pressure follows Eq. (1)."""
+    m = oracle_mod.ALTERNATE if mode == "alternate" else oracle_mod.BOTH
+    s, s_fac, dp = _coupled_1to3(oracle_mod, m, 3000)
+    ua, pa, aa = s.iolet_stats(0)
+    ub, pb, ab = s.iolet_stats(1)
+    ratios = ub[:3] / ua[1]
+    assert np.abs(ratios - s_fac).max() < 0.02 * s_fac.max(), (ratios, s_fac)
+    flux_a = aa[1] * ua[1]
+    flux_b = (ab[:3] * ub[:3]).sum()
+    assert abs(flux_b - flux_a) / flux_a < 0.02
+    # reverse rule: arterial outlet density set from the venous inlet pressures
+    bc = s.last_bc(0)
+    expect = 1.0 + 3.0 * np.mean(pb[:3] / (1 - dp))
+    assert abs(bc[1] - expect) < 0.02 * abs(expect - 1.0)
+    assert pb[:3].min() > 0
