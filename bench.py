@@ -1,0 +1,298 @@
+#!/usr/bin/env python3
+"""MLUPS and HBM roofline of the sparse D3Q19 LBGK step on one MI355X.
+
+Workload (the branching-artery configuration): a Murray's-law tree of depth 8
+(256 outlets), root radius 40 lu, branch angles uniform in 25-45 degrees,
+seeded, voxelised in a 768^3 box with the segment length/radius ratio chosen
+so the tree fits the box; Bouzidi walls with a wall fraction q uniform in
+(0, 1] per link; tau = 0.55; steady parabolic velocity inlet (peak 0.01) at
+the root; pressure outlets at rho = 1.  Inputs are synthetic and seeded.
+
+One timed step is one lattice update of every fluid site (all kernels of the
+path: gather, boundary links, collision, store, iolet reductions, boundary
+update).  MLUPS = sites * steps / time / 1e6, timed with HIP events recorded
+on the stream the library launches on, inputs resident in HBM.
+
+Printed: one JSON line (rank 0, N = 1) with the FP32 offset-storage figure as
+``value`` and the FP64 and FP16 forms under ``variants``, each with its error
+against the FP64 GPU run (itself checked against the FP64 CPU oracle at full
+size under ``parity``); ``roofline`` for the dominant kernel (bulk-site step)
+and ``cpu_baseline`` for the oracle timed on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
+TAU = 0.55
+U_IN = 0.01
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def bytes_per_site(prec):
+    """Algorithmic HBM bytes of one bulk-site update in the two-lattice pull
+    scheme: 19 populations read and written, 18 int32 pull indices."""
+    return 2 * 19 * STORE_BYTES[prec] + 18 * 4
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_2010_04144_amd", "csrc", "hl_kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def make_ctx(hl, geo, prec, torch):
+    ctx = hl.Context(0, prec)
+    d = ctx.add_domain()
+    ctx.load_geometry(d, geo)
+    ctx.set_tau(d, TAU)
+    ctx.set_wall_mode(d, hl.HL_WALL_BOUZIDI)
+    ctx.set_inlet_velocity(d, 0, U_IN)
+    ctx.set_stream(torch.cuda.current_stream())
+    ctx.commit()
+    return ctx
+
+
+def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms):
+    ctx = make_ctx(hl, geo, prec, torch)
+    if autotune_ms > 0:
+        ctx.autotune(autotune_ms)
+    ctx.step(warmup)
+    ctx.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    ctx.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync()
+    ms = e0.elapsed_time(e1)
+    kb, kn = ctx.time_kernels(kernel_steps)
+    info = ctx.info()
+    u = ctx.velocity(0)
+    rho = ctx.density(0)
+    sched = ctx.schedule()
+    ctx.close()
+    n = geo.n
+    mlups = n * steps / (ms * 1e-3) / 1e6
+    B = bytes_per_site(prec)
+    bulk_bytes = info["n_bulk"] * B
+    res = {
+        "mlups": round(mlups, 1),
+        "ms_per_step": round(ms / steps, 5),
+        "wall_s": round(wall, 3),
+        "alg_GBps": round(mlups * 1e6 * B / 1e9, 1),
+        "alg_frac_peak": round(mlups * 1e6 * B / 1e9 / PEAK_HBM_GBS, 4),
+        "bulk_kernel_ms": round(kb, 5),
+        "boundary_kernel_ms": round(kn, 5),
+        "bulk_kernel_GBps": round(bulk_bytes / (kb * 1e-3) / 1e9, 1),
+        "bytes_per_site": B,
+        "n_bulk": info["n_bulk"],
+        "n_boundary": info["n_boundary"],
+        "block": sched[0],
+        "sched_flags": sched[1],
+    }
+    log(prec, json.dumps(res))
+    return res, u, rho
+
+
+def rel_err(a, b, scale):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(scale)))
+
+
+def cpu_baseline_and_parity(hl, torch, geo, seconds, threads):
+    """Time the FP64 oracle on this host's cores over a bounded number of
+    steps of the same workload, then run the FP64 GPU path for the same
+    steps and compare."""
+    import oracle
+    sysm = oracle.System(1)
+    sysm.set_geometry(0, geo)
+    sysm.set_params(0, TAU, oracle.BOUZIDI)
+    io = geo.iolets[0]
+    sysm.set_iolet(0, 0, oracle.INLET, io.centre, io.normal, io.radius, U_IN)
+    sysm.init()
+    t0 = time.perf_counter()
+    sysm.step(1, threads)
+    t1 = time.perf_counter() - t0
+    k = max(1, int(seconds / max(t1, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    sysm.step(k, threads)
+    tk = time.perf_counter() - t0
+    steps = k + 1
+    mlups = geo.n * k / tk / 1e6
+    log(f"oracle: {steps} steps, {tk:.1f} s timed for {k} steps, {mlups:.2f} MLUPS on {threads} threads")
+    rho_r, u_r = sysm.moments(0)
+    f_r = sysm.f(0)
+    mu_r, _, _ = sysm.iolet_stats(0)
+    del sysm
+    ctx = make_ctx(hl, geo, "f64", torch)
+    ctx.step(steps)
+    u = ctx.velocity(0)
+    rho = ctx.density(0)
+    f = ctx.populations(0)
+    mu, _ = ctx.iolet_stats(0)
+    ctx.close()
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    par = {
+        "steps": steps,
+        "e_u": rel_err(u, u_r, u_r),
+        "e_rho": rel_err(rho, rho_r, rho_r - 1.0),
+        "e_f": rel_err(f, f_r, f_r - w[:, None]),
+        "e_iolet_u": rel_err(mu, mu_r, mu_r),
+        "tolerance": 1e-12,
+    }
+    par["pass"] = all(par[k2] <= 1e-12 for k2 in ("e_u", "e_rho", "e_f", "e_iolet_u"))
+    log("full-size parity", json.dumps(par))
+    cpu = {
+        "value": round(mlups, 3),
+        "unit": "MLUPS",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"the same workload ({geo.n} sites), {k} timed steps after 1 untimed step, FP64, OpenMP over sites",
+    }
+    return cpu, par
+
+
+def traffic_from_profile(prec):
+    path = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get(prec, {}).get("bulk_bytes_per_launch")
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size for scaling the HBM byte counters."""
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--box", type=int, default=768)
+    ap.add_argument("--precisions", default="f64,f32,f16")
+    ap.add_argument("--kernel-steps", type=int, default=50)
+    ap.add_argument("--autotune-ms", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and full-size parity")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding paragraph of DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+    import paper_2010_04144_amd as hl
+    import synth
+
+    t0 = time.perf_counter()
+    geo = synth.murray_tree_c2(box=args.box)
+    log(f"geometry: {geo.n} sites, fill {geo.meta['fill']:.4f}, lambda {geo.meta['lam']:.3f}, "
+        f"{len(geo.iolets)} iolets, {geo.q.size} wall links ({time.perf_counter() - t0:.1f} s)")
+
+    precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
+    runs, fields = {}, {}
+    for p in precs:
+        runs[p], fields[p] = None, None
+        res, u, rho = run_precision(hl, torch, geo, p, args.steps, args.warmup, args.kernel_steps, args.autotune_ms)
+        runs[p] = res
+        fields[p] = (u, rho)
+    if "f64" in fields:
+        u64, r64 = fields["f64"]
+        for p in precs:
+            if p == "f64":
+                continue
+            u, r = fields[p]
+            runs[p]["error_vs_f64"] = {"e_u": rel_err(u, u64, u64), "e_rho": rel_err(r, r64, r64 - 1.0),
+                                       "after_steps": args.warmup + args.steps + args.kernel_steps}
+
+    cpu, parity = None, None
+    if not args.no_cpu:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        cpu, parity = cpu_baseline_and_parity(hl, torch, geo, args.cpu_seconds, threads)
+
+    head = "f32" if "f32" in runs else precs[0]
+    r = runs[head]
+    B = r["bytes_per_site"]
+    achieved = r["bulk_kernel_GBps"]
+    traffic = traffic_from_profile(head)
+    line = {
+        "metric": "MLUPS + achieved HBM GB/s (% peak), FP64 vs FP32 at stated error, 1 GPU",
+        "value": r["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {
+            "workload": "branching artery: Murray tree depth 8, root radius 40 lu, 768^3 box, Bouzidi walls, tau 0.55",
+            "sites": geo.n,
+            "fill": round(geo.meta["fill"], 5),
+            "box": args.box,
+            "segment_length_over_radius": round(geo.meta["lam"], 4),
+            "iolets": len(geo.iolets),
+            "storage": {"f64": "FP64", "f32": "FP32 offset f - w rho0", "f16": "FP16 offset f - w rho0"}[head],
+            "arithmetic": "FP64" if head == "f64" else "FP32",
+            "scheme": "two-lattice pull, int32 pull table",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_step bulk sites (" + head + ")",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_site": B,
+            "sites_per_launch": r["n_bulk"],
+        },
+        "variants": runs,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

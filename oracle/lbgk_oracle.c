@@ -323,9 +323,11 @@ static void body_force(const domain_t *d, int64_t t, double *F) {
 }
 
 /* Step 1: moments of the current f at every site. */
-static void moments(domain_t *d, int64_t t) {
+static void moments(domain_t *d, int64_t t, int nthreads) {
     double F[3];
     body_force(d, t, F);
+    (void)nthreads;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int64_t x = 0; x < d->n; ++x) {
         double fl[Q], r, u[3];
         for (int i = 0; i < Q; ++i) fl[i] = d->f[(size_t)i * d->n + x];
@@ -335,28 +337,38 @@ static void moments(domain_t *d, int64_t t) {
     }
 }
 
-/* Step 2: means over the sites that border each iolet. */
+/* Step 2: means over the sites that border each iolet.  One pass over the
+ * sites in caller order; a site adds to every iolet it borders. */
 static void iolet_means(domain_t *d) {
+    double *su = (double *)calloc((size_t)(d->n_iolet + 1), sizeof(double));
+    double *sr = (double *)calloc((size_t)(d->n_iolet + 1), sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)(d->n_iolet + 1), sizeof(int64_t));
+    for (int64_t x = 0; x < d->n; ++x) {
+        int ks[Q], nk = 0;
+        for (int i = 1; i < Q; ++i) {
+            int32_t v = d->nbr[(size_t)i * d->n + x];
+            if (v > -2) continue;
+            int k = -2 - v, seen = 0;
+            for (int m = 0; m < nk; ++m)
+                if (ks[m] == k) seen = 1;
+            if (!seen) ks[nk++] = k;
+        }
+        for (int m = 0; m < nk; ++m) {
+            int k = ks[m];
+            double un = 0.0;
+            for (int a = 0; a < 3; ++a) un = un + d->u[(size_t)a * d->n + x] * d->io[k].nrm[a];
+            su[k] = su[k] + un;
+            sr[k] = sr[k] + d->rho[x];
+            cnt[k] = cnt[k] + 1;
+        }
+    }
     for (int k = 0; k < d->n_iolet; ++k) {
         iolet_t *io = &d->io[k];
-        int32_t code = -2 - k;
-        double su = 0.0, sr = 0.0;
-        int64_t cnt = 0;
-        for (int64_t x = 0; x < d->n; ++x) {
-            int adj = 0;
-            for (int i = 1; i < Q; ++i)
-                if (d->nbr[(size_t)i * d->n + x] == code) adj = 1;
-            if (!adj) continue;
-            double un = 0.0;
-            for (int a = 0; a < 3; ++a) un = un + d->u[(size_t)a * d->n + x] * io->nrm[a];
-            su = su + un;
-            sr = sr + d->rho[x];
-            cnt = cnt + 1;
-        }
-        io->area = cnt;
-        io->mean_u = cnt ? su / (double)cnt : 0.0;
-        io->mean_rho = cnt ? sr / (double)cnt : RHO0;
+        io->area = cnt[k];
+        io->mean_u = cnt[k] ? su[k] / (double)cnt[k] : 0.0;
+        io->mean_rho = cnt[k] ? sr[k] / (double)cnt[k] : RHO0;
     }
+    free(su); free(sr); free(cnt);
 }
 
 /* Step 3: boundary values for the stream that follows step t. */
@@ -460,21 +472,32 @@ int or_init(or_sys *s) {
         domain_t *d = &s->d[k];
         for (int i = 0; i < Q; ++i)
             for (int64_t x = 0; x < d->n; ++x) d->f[(size_t)i * d->n + x] = W[i] * RHO0;
+        /* mean inlet profile factor over each iolet's bordering sites,
+         * one pass over the sites in caller order */
+        double *sp = (double *)calloc((size_t)(d->n_iolet + 1), sizeof(double));
+        int64_t *cnt = (int64_t *)calloc((size_t)(d->n_iolet + 1), sizeof(int64_t));
+        for (int64_t x = 0; x < d->n; ++x) {
+            int ks[Q], nk = 0;
+            for (int i = 1; i < Q; ++i) {
+                int32_t v = d->nbr[(size_t)i * d->n + x];
+                if (v > -2) continue;
+                int k = -2 - v, seen = 0;
+                for (int m = 0; m < nk; ++m)
+                    if (ks[m] == k) seen = 1;
+                if (!seen) ks[nk++] = k;
+            }
+            for (int m = 0; m < nk; ++m) {
+                sp[ks[m]] = sp[ks[m]] + profile(&d->io[ks[m]], d->coords, d->n, x);
+                cnt[ks[m]] = cnt[ks[m]] + 1;
+            }
+        }
         for (int j = 0; j < d->n_iolet; ++j) {
             iolet_t *io = &d->io[j];
             io->held = series_at(&io->wave, 0.0);
-            double sp = 0.0;
-            int64_t cnt = 0;
-            for (int64_t x = 0; x < d->n; ++x) {
-                int adj = 0;
-                for (int i = 1; i < Q; ++i)
-                    if (d->nbr[(size_t)i * d->n + x] == -2 - j) adj = 1;
-                if (!adj) continue;
-                sp = sp + profile(io, d->coords, d->n, x);
-                cnt = cnt + 1;
-            }
-            io->phibar = cnt ? sp / (double)cnt : 0.0;
+            io->phibar = cnt[j] ? sp[j] / (double)cnt[j] : 0.0;
         }
+        free(sp);
+        free(cnt);
     }
     s->ready = 1;
     return 0;
@@ -491,7 +514,7 @@ int or_step(or_sys *s, int64_t nsteps, int nthreads) {
     if (nthreads < 1) nthreads = 1;
     for (int64_t it = 0; it < nsteps; ++it) {
         for (int k = 0; k < s->ndom; ++k) {
-            moments(&s->d[k], s->t);
+            moments(&s->d[k], s->t, nthreads);
             iolet_means(&s->d[k]);
         }
         boundary_values(s);
@@ -524,7 +547,7 @@ int or_read_fpost(or_sys *s, int dom, double *f) {
 
 int or_read_moments(or_sys *s, int dom, double *rho, double *u) {
     domain_t *d = &s->d[dom];
-    moments(d, s->t);
+    moments(d, s->t, 1);
     memcpy(rho, d->rho, (size_t)d->n * sizeof(double));
     memcpy(u, d->u, 3 * (size_t)d->n * sizeof(double));
     return 0;
@@ -534,7 +557,7 @@ int or_read_moments(or_sys *s, int dom, double *rho, double *u) {
  * will use (both recomputed from the current state). */
 int or_read_iolet_stats(or_sys *s, int dom, double *mean_u, double *mean_p, int64_t *area) {
     for (int k = 0; k < s->ndom; ++k) {
-        moments(&s->d[k], s->t);
+        moments(&s->d[k], s->t, 1);
         iolet_means(&s->d[k]);
     }
     domain_t *d = &s->d[dom];
@@ -552,7 +575,7 @@ int or_read_iolet_stats(or_sys *s, int dom, double *mean_u, double *mean_p, int6
  * -sum of the wall-link directions. */
 int or_read_wss(or_sys *s, int dom, double *wss) {
     domain_t *d = &s->d[dom];
-    moments(d, s->t);
+    moments(d, s->t, 1);
     const int64_t n = d->n;
     for (int64_t x = 0; x < n; ++x) {
         double nv[3] = {0.0, 0.0, 0.0};

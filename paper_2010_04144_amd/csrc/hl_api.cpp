@@ -1,0 +1,1312 @@
+// Host side of the C ABI declared in include/hemelb_hip.h: argument checks,
+// the internal site order and pull table, the work-group schedule, device
+// memory, the step driver (plain launches or a replayed HIP graph), reads,
+// checkpoints and the schedule autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hemelb_hip.h"
+#include "hl_internal.h"
+
+using hl::Q;
+
+namespace {
+
+constexpr int CXh[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CYh[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZh[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+inline int opp_h(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+struct Series {
+    double a0 = 0.0;
+    int nh = 0;
+    double a[hl::MAXH] = {0}, b[hl::MAXH] = {0};
+    double period = 1.0;
+    double at(double t) const {
+        double v = a0;
+        for (int m = 1; m <= nh; ++m) {
+            const double ph = 2.0 * M_PI * (double)m * t / period;
+            v = v + a[m - 1] * std::cos(ph) + b[m - 1] * std::sin(ph);
+        }
+        return v;
+    }
+    double bound() const {
+        double v = std::fabs(a0);
+        for (int m = 0; m < nh; ++m) v += std::fabs(a[m]) + std::fabs(b[m]);
+        return v;
+    }
+};
+
+struct IoletH {
+    int kind = hl::KIND_INLET;
+    double c[3] = {0, 0, 0}, nrm[3] = {0, 0, 1}, R = 1.0;
+    Series wave;
+    bool coupled = false;
+};
+
+struct Domain {
+    int64_t n = 0;
+    std::vector<int32_t> coords, nbr;
+    std::vector<int64_t> q_site;
+    std::vector<int8_t> q_dir;
+    std::vector<float> q;
+    std::vector<int64_t> wn_site;
+    std::vector<double> wn;
+    int32_t n_iolet = 0;
+    std::vector<IoletH> io;
+    double tau = 1.0;
+    int wall_mode = hl::WALL_SBB;
+    double F0[3] = {0, 0, 0}, omega = 0.0;
+    // after commit
+    std::vector<int64_t> c2g;
+    int32_t io_base = 0;
+    int64_t *d_c2g = nullptr;
+};
+
+struct PairH {
+    int da, ka, db, kb;
+    double s, delta;
+};
+
+// a contiguous internal range of one class in one domain
+struct Range {
+    int64_t start, count;
+    int32_t seg, tag;
+};
+
+}  // namespace
+
+struct hl_ctx {
+    int device = 0, precision = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+    std::vector<Domain> doms;
+    std::vector<PairH> pairs;
+    int couple_mode = hl::COUPLE_ALTERNATE;
+    bool committed = false;
+    int block = 256;
+    int sched_flags = 0;
+    int drive = HL_DRIVE_GRAPH;
+    int steps_per_graph = 16;
+    int64_t t_host = 0;
+    // layout
+    int64_t N = 0, NB = 0, IO0 = 0, Nb = 0, Nio = 0;
+    std::vector<Range> ranges;
+    int n_bulk_ranges = 0;
+    std::vector<hl::Entry> entries;
+    int n_bulk_blocks = 0, n_bnd_blocks = 0;
+    std::vector<hl::SegDev> hseg;
+    std::vector<hl::IoletDev> hio;
+    std::vector<hl::PairDev> hpairs;
+    // device memory
+    void *lat[2] = {nullptr, nullptr};
+    int32_t *d_src = nullptr;
+    float *d_bq = nullptr;
+    double *d_bphi = nullptr, *d_bnrm = nullptr;
+    void *d_up[2] = {nullptr, nullptr};
+    hl::Entry *d_entries = nullptr;
+    hl::SegDev *d_seg = nullptr;
+    hl::IoletDev *d_io = nullptr;
+    hl::PairDev *d_pairs = nullptr;
+    hl::Ctrl *d_ctrl = nullptr;
+    double *d_partials = nullptr, *d_stats = nullptr, *d_bc = nullptr, *d_held = nullptr;
+    double *d_obs = nullptr, *d_fbuf = nullptr;
+    int64_t dev_bytes = 0;
+    int64_t obs_t = -1;
+    hipGraphExec_t gexec = nullptr;
+    int graph_steps = 0;
+    int *h_nan = nullptr;  // pinned copy of the divergence flag
+};
+
+namespace {
+
+int fail(hl_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPC(ctx, call)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? HL_E_NOMEM : HL_E_DEVICE, "%s: %s", #call, \
+                        hipGetErrorString(e_));                                                 \
+    } while (0)
+
+size_t store_bytes(int prec) { return prec == hl::PREC_F64 ? 8 : (prec == hl::PREC_F32 ? 4 : 2); }
+size_t arith_bytes(int prec) { return prec == hl::PREC_F64 ? 8 : 4; }
+
+int check_dom(hl_ctx *c, int32_t dom) {
+    if (!c) return HL_E_INVAL;
+    if (dom < 0 || dom >= (int32_t)c->doms.size()) return fail(c, HL_E_RANGE, "domain %d does not exist", dom);
+    return HL_OK;
+}
+
+template <typename T>
+int dalloc(hl_ctx *c, T **p, size_t count) {
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, HL_E_NOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->dev_bytes += (int64_t)bytes;
+    return HL_OK;
+}
+
+void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+void free_device(hl_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->graph_steps = 0;
+    void *ps[] = {c->lat[0], c->lat[1], c->d_src, c->d_bq, c->d_bphi, c->d_bnrm, c->d_up[0], c->d_up[1],
+                  c->d_entries, c->d_seg, c->d_io, c->d_pairs, c->d_ctrl, c->d_partials, c->d_stats,
+                  c->d_bc, c->d_held, c->d_obs, c->d_fbuf};
+    for (void *p : ps) dfree(p);
+    for (auto &d : c->doms) {
+        dfree(d.d_c2g);
+        d.d_c2g = nullptr;
+    }
+    c->lat[0] = c->lat[1] = nullptr;
+    c->d_src = nullptr;
+    c->d_bq = nullptr;
+    c->d_bphi = c->d_bnrm = nullptr;
+    c->d_up[0] = c->d_up[1] = nullptr;
+    c->d_entries = nullptr;
+    c->d_seg = nullptr;
+    c->d_io = nullptr;
+    c->d_pairs = nullptr;
+    c->d_ctrl = nullptr;
+    c->d_partials = c->d_stats = c->d_bc = c->d_held = c->d_obs = c->d_fbuf = nullptr;
+    c->dev_bytes = 0;
+}
+
+hl::SegDev seg_of(const Domain &d) {
+    hl::SegDev s{};
+    s.inv_tau = 1.0 / d.tau;
+    s.guo_pref = 1.0 - 1.0 / (2.0 * d.tau);
+    for (int k = 0; k < 3; ++k) s.F0[k] = d.F0[k];
+    s.omega = d.omega;
+    s.wall_mode = d.wall_mode;
+    s.has_force = (d.F0[0] != 0.0 || d.F0[1] != 0.0 || d.F0[2] != 0.0) ? 1 : 0;
+    return s;
+}
+
+hl::KArgs make_args(hl_ctx *c) {
+    hl::KArgs a{};
+    a.N = c->N;
+    a.NB = c->NB;
+    a.IO0 = c->IO0;
+    a.Nb = c->Nb;
+    a.Nio = c->Nio;
+    a.lat0 = c->lat[0];
+    a.lat1 = c->lat[1];
+    a.src = c->d_src;
+    a.bq = c->d_bq;
+    a.bphi = c->d_bphi;
+    a.up0 = c->d_up[0];
+    a.up1 = c->d_up[1];
+    a.bnrm = c->d_bnrm;
+    a.entries = c->d_entries;
+    a.seg = c->d_seg;
+    a.io = c->d_io;
+    a.pairs = c->d_pairs;
+    a.n_io = (int32_t)c->hio.size();
+    a.n_pairs = (int32_t)c->hpairs.size();
+    a.couple_mode = c->couple_mode;
+    a.xcd_remap = (c->sched_flags & HL_SCHED_XCD_REMAP) ? 1 : 0;
+    a.ctrl = c->d_ctrl;
+    a.partials = c->d_partials;
+    a.stats = c->d_stats;
+    a.bc = c->d_bc;
+    a.held = c->d_held;
+    a.obs = c->d_obs;
+    a.fout = nullptr;
+    a.fin = nullptr;
+    return a;
+}
+
+// Split the class ranges into work-group entries of at most `block` sites.
+void build_entries(hl_ctx *c) {
+    c->entries.clear();
+    for (auto &io : c->hio) io.e_lo = io.e_hi = 0;
+    int nb = 0;
+    for (size_t r = 0; r < c->ranges.size(); ++r) {
+        const Range &g = c->ranges[r];
+        const int klass = g.tag & 3;
+        const int first = (int)c->entries.size();
+        for (int64_t off = 0; off < g.count; off += c->block) {
+            hl::Entry e;
+            e.start = (int32_t)(g.start + off);
+            e.count = (int32_t)std::min<int64_t>(c->block, g.count - off);
+            e.seg = g.seg;
+            e.tag = g.tag;
+            c->entries.push_back(e);
+        }
+        if (klass == hl::K_IOLET) {
+            auto &io = c->hio[g.tag >> 2];
+            io.e_lo = first;
+            io.e_hi = (int)c->entries.size();
+        }
+        if ((int)r < c->n_bulk_ranges) nb = (int)c->entries.size();
+    }
+    c->n_bulk_blocks = nb;
+    c->n_bnd_blocks = (int)c->entries.size() - nb;
+}
+
+int upload_schedule(hl_ctx *c) {
+    dfree(c->d_entries);
+    dfree(c->d_partials);
+    c->d_entries = nullptr;
+    c->d_partials = nullptr;
+    int rc;
+    if ((rc = dalloc(c, &c->d_entries, c->entries.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_partials, 2 * c->entries.size())) != HL_OK) return rc;
+    HIPC(c, hipMemcpy(c->d_entries, c->entries.data(), c->entries.size() * sizeof(hl::Entry),
+                      hipMemcpyHostToDevice));
+    if (!c->hio.empty())
+        HIPC(c, hipMemcpy(c->d_io, c->hio.data(), c->hio.size() * sizeof(hl::IoletDev), hipMemcpyHostToDevice));
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->graph_steps = 0;
+    return HL_OK;
+}
+
+int launch_steps_plain(hl_ctx *c, int64_t n, hipStream_t st) {
+    const hl::KArgs a = make_args(c);
+    for (int64_t k = 0; k < n; ++k) {
+        int e = hl::launch_step(c->precision, a, c->n_bulk_blocks, c->n_bnd_blocks, c->block, st);
+        if (e != 0) return fail(c, HL_E_DEVICE, "step launch failed: %s", hipGetErrorString((hipError_t)e));
+    }
+    return HL_OK;
+}
+
+int ensure_graph(hl_ctx *c) {
+    if (c->gexec && c->graph_steps == c->steps_per_graph) return HL_OK;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    if (!c->cap_stream) HIPC(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPC(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_steps_plain(c, c->steps_per_graph, c->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc != HL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, HL_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, HL_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    c->graph_steps = c->steps_per_graph;
+    return HL_OK;
+}
+
+int run_steps(hl_ctx *c, int64_t n) {
+    int64_t rest = n;
+    if (c->drive == HL_DRIVE_GRAPH && n >= c->steps_per_graph) {
+        int rc = ensure_graph(c);
+        if (rc != HL_OK) return rc;
+        while (rest >= c->graph_steps) {
+            HIPC(c, hipGraphLaunch(c->gexec, c->stream));
+            rest -= c->graph_steps;
+        }
+    }
+    int rc = launch_steps_plain(c, rest, c->stream);
+    if (rc != HL_OK) return rc;
+    c->t_host += n;
+    c->obs_t = -1;
+    HIPC(c, hipMemcpyAsync(c->h_nan, &c->d_ctrl->nan_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    return HL_OK;
+}
+
+int upload_params(hl_ctx *c) {
+    if (!c->committed) return HL_OK;
+    for (size_t d = 0; d < c->doms.size(); ++d) c->hseg[d] = seg_of(c->doms[d]);
+    HIPC(c, hipStreamSynchronize(c->stream));
+    HIPC(c, hipMemcpy(c->d_seg, c->hseg.data(), c->hseg.size() * sizeof(hl::SegDev), hipMemcpyHostToDevice));
+    return HL_OK;
+}
+
+// Re-evaluate the boundary value of an uncoupled iolet for the coming step
+// after its waveform changed.
+int refresh_series(hl_ctx *c, int32_t dom, int32_t k) {
+    if (!c->committed) return HL_OK;
+    Domain &d = c->doms[dom];
+    const int g = d.io_base + k;
+    hl::IoletDev &io = c->hio[g];
+    const Series &s = d.io[k].wave;
+    io.a0 = s.a0;
+    io.nh = s.nh;
+    io.period = s.period;
+    for (int m = 0; m < hl::MAXH; ++m) {
+        io.a[m] = s.a[m];
+        io.b[m] = s.b[m];
+    }
+    HIPC(c, hipStreamSynchronize(c->stream));
+    HIPC(c, hipMemcpy(c->d_io + g, &io, sizeof io, hipMemcpyHostToDevice));
+    if (!io.coupled) {
+        const double v = s.at((double)c->t_host);
+        HIPC(c, hipMemcpy(c->d_bc + (c->t_host & 1) * c->hio.size() + g, &v, sizeof v, hipMemcpyHostToDevice));
+    }
+    return HL_OK;
+}
+
+int read_nan(hl_ctx *c) {
+    HIPC(c, hipStreamSynchronize(c->stream));
+    int v = 0;
+    HIPC(c, hipMemcpy(&v, &c->d_ctrl->nan_flag, sizeof v, hipMemcpyDeviceToHost));
+    *c->h_nan = v;
+    if (v) return fail(c, HL_E_DIVERGED, "a non-finite density appeared");
+    return HL_OK;
+}
+
+int observe(hl_ctx *c, bool with_f) {
+    int rc;
+    if (!c->d_obs && (rc = dalloc(c, &c->d_obs, 5 * (size_t)c->N)) != HL_OK) return rc;
+    if (with_f && !c->d_fbuf && (rc = dalloc(c, &c->d_fbuf, (size_t)Q * c->N)) != HL_OK) return rc;
+    if (!with_f && c->obs_t == c->t_host) return HL_OK;
+    hl::KArgs a = make_args(c);
+    a.fout = with_f ? c->d_fbuf : nullptr;
+    int e = hl::launch_observe(c->precision, a, (int)c->entries.size(), c->block, c->stream);
+    if (e != 0) return fail(c, HL_E_DEVICE, "observe launch failed: %s", hipGetErrorString((hipError_t)e));
+    c->obs_t = c->t_host;
+    return HL_OK;
+}
+
+// Collide the raw f(t) in lat[(t+1)&1] into f*(t) and recompute the means
+// and boundary values of step t.
+int reinit(hl_ctx *c) {
+    hl::KArgs a = make_args(c);
+    int e = hl::launch_init(c->precision, a, (int)c->entries.size(), c->block, c->stream);
+    if (e != 0) return fail(c, HL_E_DEVICE, "init launch failed: %s", hipGetErrorString((hipError_t)e));
+    c->obs_t = -1;
+    return HL_OK;
+}
+
+int commit(hl_ctx *c) {
+    if (c->committed) return HL_OK;
+    int64_t total = 0;
+    for (auto &d : c->doms) total += d.n;
+    if (total == 0) return fail(c, HL_E_STATE, "no domain holds a site");
+    if (total > INT32_MAX) return fail(c, HL_E_RANGE, "more than 2^31-1 sites in one context");
+    HIPC(c, hipSetDevice(c->device));
+    const int D = (int)c->doms.size();
+
+    // classes: 0 bulk, 1 wall only, 2 iolet k
+    std::vector<std::vector<int32_t>> cls(D);  // -1 bulk, -2 wall, k >= 0 iolet
+    int32_t io_count = 0;
+    for (int d = 0; d < D; ++d) {
+        Domain &dm = c->doms[d];
+        dm.io_base = io_count;
+        io_count += dm.n_iolet;
+        cls[d].assign(dm.n, -1);
+        for (int64_t x = 0; x < dm.n; ++x) {
+            int32_t k = -1;
+            bool wall = false;
+            for (int i = 1; i < Q; ++i) {
+                const int32_t v = dm.nbr[(size_t)i * dm.n + x];
+                if (v == -1) wall = true;
+                if (v <= -2) k = -2 - v;
+            }
+            cls[d][x] = k >= 0 ? k : (wall ? -2 : -1);
+        }
+    }
+    // internal order
+    c->ranges.clear();
+    int64_t pos = 0;
+    for (int d = 0; d < D; ++d) {
+        Domain &dm = c->doms[d];
+        dm.c2g.assign(dm.n, -1);
+        const int64_t st = pos;
+        for (int64_t x = 0; x < dm.n; ++x)
+            if (cls[d][x] == -1) dm.c2g[x] = pos++;
+        if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_BULK});
+    }
+    c->n_bulk_ranges = (int)c->ranges.size();
+    c->NB = pos;
+    for (int d = 0; d < D; ++d) {
+        Domain &dm = c->doms[d];
+        const int64_t st = pos;
+        for (int64_t x = 0; x < dm.n; ++x)
+            if (cls[d][x] == -2) dm.c2g[x] = pos++;
+        if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_WALL});
+    }
+    c->IO0 = pos;
+    std::vector<int64_t> io_lo(io_count, 0), io_n(io_count, 0);
+    for (int d = 0; d < D; ++d) {
+        Domain &dm = c->doms[d];
+        for (int k = 0; k < dm.n_iolet; ++k) {
+            const int64_t st = pos;
+            for (int64_t x = 0; x < dm.n; ++x)
+                if (cls[d][x] == k) dm.c2g[x] = pos++;
+            io_lo[dm.io_base + k] = st;
+            io_n[dm.io_base + k] = pos - st;
+            if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_IOLET | ((dm.io_base + k) << 2)});
+        }
+    }
+    c->N = pos;
+    c->Nb = c->N - c->NB;
+    c->Nio = c->N - c->IO0;
+    const int64_t N = c->N, NB = c->NB, Nb = c->Nb, Nio = c->Nio;
+
+    // pull table, wall fractions, inlet profile, wall normals
+    std::vector<int32_t> src((size_t)18 * N);
+    std::vector<float> bq((size_t)18 * std::max<int64_t>(Nb, 1), 0.5f);
+    std::vector<double> bphi(std::max<int64_t>(Nb, 1), 0.0), bnrm((size_t)3 * std::max<int64_t>(Nb, 1), 0.0);
+    c->hio.assign(io_count, hl::IoletDev{});
+    for (int d = 0; d < D; ++d) {
+        Domain &dm = c->doms[d];
+        for (int64_t x = 0; x < dm.n; ++x) {
+            const int64_t g = dm.c2g[x];
+            for (int j = 1; j < Q; ++j) {
+                const int32_t up = dm.nbr[(size_t)opp_h(j) * dm.n + x];
+                int32_t v;
+                if (up >= 0)
+                    v = (int32_t)dm.c2g[up];
+                else if (up == -1)
+                    v = -1;
+                else
+                    v = -2 - (dm.io_base + (-2 - up));
+                src[(size_t)(j - 1) * N + g] = v;
+            }
+        }
+        for (size_t e = 0; e < dm.q.size(); ++e) {
+            const int64_t g = dm.c2g[dm.q_site[e]];
+            const int j = opp_h(dm.q_dir[e]);
+            bq[(size_t)(j - 1) * Nb + (g - NB)] = dm.q[e];
+        }
+        std::vector<double> userw;
+        std::vector<char> has_user;
+        if (!dm.wn_site.empty()) {
+            userw.assign((size_t)3 * dm.n, 0.0);
+            has_user.assign(dm.n, 0);
+            const size_t nw = dm.wn_site.size();
+            for (size_t e = 0; e < nw; ++e) {
+                const int64_t x = dm.wn_site[e];
+                has_user[x] = 1;
+                for (int a = 0; a < 3; ++a) userw[(size_t)a * dm.n + x] = dm.wn[a * nw + e];
+            }
+        }
+        for (int64_t x = 0; x < dm.n; ++x) {
+            const int64_t g = dm.c2g[x];
+            if (g < NB) continue;
+            const int64_t b = g - NB;
+            double nv[3] = {0, 0, 0};
+            bool wall = false;
+            for (int i = 1; i < Q; ++i)
+                if (dm.nbr[(size_t)i * dm.n + x] == -1) {
+                    wall = true;
+                    nv[0] -= CXh[i];
+                    nv[1] -= CYh[i];
+                    nv[2] -= CZh[i];
+                }
+            if (wall) {
+                if (!has_user.empty() && has_user[x])
+                    for (int a = 0; a < 3; ++a) nv[a] = userw[(size_t)a * dm.n + x];
+                const double nl = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+                if (nl > 0.0)
+                    for (int a = 0; a < 3; ++a) bnrm[(size_t)a * Nb + b] = nv[a] / nl;
+            }
+            const int32_t k = cls[d][x];
+            if (k >= 0 && dm.io[k].kind == hl::KIND_INLET) {
+                const IoletH &io = dm.io[k];
+                double dv[3], dn = 0.0, dd = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    dv[a] = (double)dm.coords[(size_t)a * dm.n + x] - io.c[a];
+                    dn = dn + dv[a] * io.nrm[a];
+                    dd = dd + dv[a] * dv[a];
+                }
+                const double r2 = dd - dn * dn;
+                const double v = 1.0 - r2 / (io.R * io.R);
+                bphi[b] = v > 0.0 ? v : 0.0;
+            }
+        }
+        for (int k = 0; k < dm.n_iolet; ++k) {
+            const int g = dm.io_base + k;
+            hl::IoletDev &io = c->hio[g];
+            const IoletH &ih = dm.io[k];
+            for (int a = 0; a < 3; ++a) io.nrm[a] = ih.nrm[a];
+            io.area = (double)io_n[g];
+            double sp = 0.0;
+            for (int64_t s = io_lo[g]; s < io_lo[g] + io_n[g]; ++s) sp = sp + bphi[s - NB];
+            io.phibar = io_n[g] ? sp / (double)io_n[g] : 0.0;
+            io.a0 = ih.wave.a0;
+            io.nh = ih.wave.nh;
+            io.period = ih.wave.period;
+            for (int m = 0; m < hl::MAXH; ++m) {
+                io.a[m] = ih.wave.a[m];
+                io.b[m] = ih.wave.b[m];
+            }
+            io.kind = ih.kind;
+            io.coupled = ih.coupled ? 1 : 0;
+            io.seg = d;
+        }
+    }
+    // coupling pairs grouped by arterial outlet, call order kept
+    c->hpairs.clear();
+    {
+        std::vector<size_t> order(c->pairs.size());
+        for (size_t p = 0; p < order.size(); ++p) order[p] = p;
+        auto outg = [&](size_t p) { return c->doms[c->pairs[p].da].io_base + c->pairs[p].ka; };
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return outg(x) < outg(y); });
+        for (size_t p : order) {
+            const PairH &ph = c->pairs[p];
+            hl::PairDev pd;
+            pd.out_g = c->doms[ph.da].io_base + ph.ka;
+            pd.in_g = c->doms[ph.db].io_base + ph.kb;
+            pd.s = ph.s;
+            pd.delta = ph.delta;
+            hl::IoletDev &o = c->hio[pd.out_g];
+            if (o.pair_n == 0) o.pair_lo = (int32_t)c->hpairs.size();
+            o.pair_n++;
+            c->hpairs.push_back(pd);
+        }
+    }
+    c->hseg.clear();
+    for (auto &d : c->doms) c->hseg.push_back(seg_of(d));
+    build_entries(c);
+
+    // device memory
+    const size_t S = store_bytes(c->precision), A = arith_bytes(c->precision);
+    int rc;
+    for (int p = 0; p < 2; ++p) {
+        HIPC(c, hipMalloc(&c->lat[p], (size_t)Q * N * S));
+        c->dev_bytes += (int64_t)((size_t)Q * N * S);
+        HIPC(c, hipMalloc(&c->d_up[p], std::max<size_t>((size_t)3 * Nio * A, 8)));
+        c->dev_bytes += (int64_t)std::max<size_t>((size_t)3 * Nio * A, 8);
+    }
+    if ((rc = dalloc(c, &c->d_src, src.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_bq, bq.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_bphi, bphi.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_bnrm, bnrm.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_seg, c->hseg.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_io, c->hio.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_pairs, c->hpairs.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_ctrl, 1)) != HL_OK) return rc;
+    const size_t nio1 = std::max<size_t>(c->hio.size(), 1);
+    if ((rc = dalloc(c, &c->d_stats, 2 * nio1)) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_bc, 2 * nio1)) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_held, nio1)) != HL_OK) return rc;
+    HIPC(c, hipMemcpy(c->d_src, src.data(), src.size() * 4, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_bq, bq.data(), bq.size() * 4, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_bphi, bphi.data(), bphi.size() * 8, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_bnrm, bnrm.data(), bnrm.size() * 8, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_seg, c->hseg.data(), c->hseg.size() * sizeof(hl::SegDev), hipMemcpyHostToDevice));
+    if (!c->hpairs.empty())
+        HIPC(c, hipMemcpy(c->d_pairs, c->hpairs.data(), c->hpairs.size() * sizeof(hl::PairDev),
+                          hipMemcpyHostToDevice));
+    if ((rc = upload_schedule(c)) != HL_OK) return rc;
+    std::vector<double> held(nio1, 0.0), zeros(2 * nio1, 0.0);
+    for (int d = 0; d < D; ++d)
+        for (int k = 0; k < c->doms[d].n_iolet; ++k) held[c->doms[d].io_base + k] = c->doms[d].io[k].wave.at(0.0);
+    HIPC(c, hipMemcpy(c->d_held, held.data(), held.size() * 8, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_bc, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_stats, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice));
+    hl::Ctrl ctrl{};
+    HIPC(c, hipMemcpy(c->d_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
+    // geometry arrays are no longer needed on the host
+    for (auto &d : c->doms) {
+        std::vector<int32_t>().swap(d.nbr);
+        std::vector<int32_t>().swap(d.coords);
+    }
+    c->committed = true;
+    c->t_host = 0;
+    // initial state: rest equilibrium at rho0, collided into f*(0)
+    hl::KArgs a = make_args(c);
+    int e = hl::launch_fill_rest(c->precision, a, c->stream);
+    if (e != 0) return fail(c, HL_E_DEVICE, "fill launch failed: %s", hipGetErrorString((hipError_t)e));
+    if ((rc = reinit(c)) != HL_OK) return rc;
+    HIPC(c, hipStreamSynchronize(c->stream));
+    return HL_OK;
+}
+
+int validate(hl_ctx *c, int64_t n, const int32_t *nbr, int64_t n_iolet) {
+    if (n < 0 || n > INT32_MAX) return fail(c, HL_E_RANGE, "site count %lld out of range", (long long)n);
+    if (n_iolet < 0 || n_iolet > (1 << 20)) return fail(c, HL_E_RANGE, "iolet count out of range");
+    if (n > 0 && !nbr) return fail(c, HL_E_INVAL, "nbr is NULL");
+    for (int64_t x = 0; x < n; ++x)
+        if (nbr[x] != x) return fail(c, HL_E_RANGE, "nbr[0][%lld] must equal the site index", (long long)x);
+    for (int i = 1; i < Q; ++i) {
+        const int32_t *row = nbr + (size_t)i * n;
+        const int32_t *back = nbr + (size_t)opp_h(i) * n;
+        for (int64_t x = 0; x < n; ++x) {
+            const int32_t v = row[x];
+            if (v >= 0) {
+                if (v >= n) return fail(c, HL_E_RANGE, "nbr[%d][%lld] = %d >= n", i, (long long)x, v);
+                if (back[v] != x)
+                    return fail(c, HL_E_INVAL, "link (%lld, %d) has no reverse link", (long long)x, i);
+            } else if (v < -1 - n_iolet) {
+                return fail(c, HL_E_RANGE, "nbr[%d][%lld] = %d is not a known code", i, (long long)x, v);
+            }
+        }
+    }
+    for (int64_t x = 0; x < n; ++x) {
+        int32_t k = 0;
+        for (int i = 1; i < Q; ++i) {
+            const int32_t v = nbr[(size_t)i * n + x];
+            if (v <= -2) {
+                if (k != 0 && k != v)
+                    return fail(c, HL_E_INVAL, "site %lld borders two iolets", (long long)x);
+                k = v;
+            }
+        }
+    }
+    return HL_OK;
+}
+
+int parse_series(hl_ctx *c, Series &s, double a0, int nh, const double *a, const double *b, double period) {
+    if (nh < 0 || nh > hl::MAXH) return fail(c, HL_E_INVAL, "nh = %d outside 0..%d", nh, hl::MAXH);
+    if (nh > 0 && (!(period > 0.0) || !a || !b)) return fail(c, HL_E_INVAL, "period must be > 0 with harmonics");
+    if (!std::isfinite(a0)) return fail(c, HL_E_INVAL, "non-finite series");
+    s = Series{};
+    s.a0 = a0;
+    s.nh = nh;
+    s.period = nh > 0 ? period : 1.0;
+    for (int m = 0; m < nh; ++m) {
+        if (!std::isfinite(a[m]) || !std::isfinite(b[m])) return fail(c, HL_E_INVAL, "non-finite series");
+        s.a[m] = a[m];
+        s.b[m] = b[m];
+    }
+    return HL_OK;
+}
+
+struct StateHeader {
+    char magic[8];
+    int32_t version, precision;
+    int64_t N, Nio, n_io, bytes;
+};
+
+size_t state_bytes(hl_ctx *c) {
+    const size_t S = store_bytes(c->precision), A = arith_bytes(c->precision);
+    const size_t nio = c->hio.size();
+    return sizeof(StateHeader) + sizeof(hl::Ctrl) + 2 * (size_t)Q * c->N * S + 2 * (size_t)3 * c->Nio * A +
+           (2 + 2 + 1) * nio * sizeof(double);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *hl_status_string(int code) {
+    switch (code) {
+        case HL_OK: return "ok";
+        case HL_E_INVAL: return "invalid argument";
+        case HL_E_RANGE: return "index or code out of range";
+        case HL_E_STATE: return "call not allowed in the current state";
+        case HL_E_NOMEM: return "allocation failed";
+        case HL_E_DEVICE: return "device error";
+        case HL_E_DIVERGED: return "simulation diverged";
+        case HL_W_MACH: return "warning: Mach number >= 0.1";
+        case HL_W_TAU: return "warning: tau > 1";
+        default: return "unknown status";
+    }
+}
+
+const char *hl_last_error(const hl_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
+    if (!out) return HL_E_INVAL;
+    *out = nullptr;
+    if (precision < HL_F64 || precision > HL_F16_OFFSET || flags != 0) return HL_E_INVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HL_E_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HL_E_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HL_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return HL_E_DEVICE;
+    hl_ctx *c = new hl_ctx();
+    c->device = device;
+    c->precision = precision;
+    if (hipHostMalloc((void **)&c->h_nan, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return HL_E_NOMEM;
+    }
+    *c->h_nan = 0;
+    *out = c;
+    return HL_OK;
+}
+
+void hl_destroy(hl_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->committed) (void)hipStreamSynchronize(ctx->stream);
+    free_device(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->h_nan) (void)hipHostFree(ctx->h_nan);
+    delete ctx;
+}
+
+int hl_set_stream(hl_ctx *ctx, void *hip_stream) {
+    if (!ctx) return HL_E_INVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return HL_OK;
+}
+
+int hl_add_domain(hl_ctx *ctx, int32_t *dom_id) {
+    if (!ctx || !dom_id) return HL_E_INVAL;
+    if (ctx->committed) return fail(ctx, HL_E_STATE, "domains cannot be added after the first step");
+    ctx->doms.emplace_back();
+    *dom_id = (int32_t)ctx->doms.size() - 1;
+    return HL_OK;
+}
+
+int hl_validate_sites(int64_t n, const int32_t *nbr, int64_t n_iolet) { return validate(nullptr, n, nbr, n_iolet); }
+
+int hl_load_sites(hl_ctx *ctx, int32_t dom, int64_t n, const int32_t *coords, const int32_t *nbr, int32_t n_iolet,
+                  int64_t n_q, const int64_t *q_site, const int8_t *q_dir, const float *q) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (ctx->committed) return fail(ctx, HL_E_STATE, "sites cannot be loaded after the first step");
+    if ((rc = validate(ctx, n, nbr, n_iolet)) != HL_OK) return rc;
+    if (n > 0 && !coords) return fail(ctx, HL_E_INVAL, "coords is NULL");
+    if (n_q < 0 || (n_q > 0 && (!q_site || !q_dir || !q))) return fail(ctx, HL_E_INVAL, "bad wall-fraction arrays");
+    for (int64_t e = 0; e < n_q; ++e) {
+        if (q_site[e] < 0 || q_site[e] >= n || q_dir[e] < 1 || q_dir[e] >= Q)
+            return fail(ctx, HL_E_RANGE, "wall fraction %lld names no link", (long long)e);
+        if (nbr[(size_t)q_dir[e] * n + q_site[e]] != -1)
+            return fail(ctx, HL_E_RANGE, "wall fraction %lld is not on a wall link", (long long)e);
+        if (!(q[e] > 0.0f && q[e] <= 1.0f)) return fail(ctx, HL_E_RANGE, "wall fraction %lld outside (0,1]", (long long)e);
+    }
+    Domain &d = ctx->doms[dom];
+    d.n = n;
+    d.coords.assign(coords, coords + 3 * (size_t)n);
+    d.nbr.assign(nbr, nbr + (size_t)Q * n);
+    d.q_site.assign(q_site, q_site + n_q);
+    d.q_dir.assign(q_dir, q_dir + n_q);
+    d.q.assign(q, q + n_q);
+    d.n_iolet = n_iolet;
+    d.io.assign(n_iolet, IoletH{});
+    for (auto &io : d.io) io.wave.a0 = 0.0;
+    d.wn_site.clear();
+    d.wn.clear();
+    return HL_OK;
+}
+
+int hl_set_wall_normals(hl_ctx *ctx, int32_t dom, int64_t n_w, const int64_t *site, const double *nrm) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (ctx->committed) return fail(ctx, HL_E_STATE, "normals cannot change after the first step");
+    Domain &d = ctx->doms[dom];
+    if (n_w < 0 || (n_w > 0 && (!site || !nrm))) return fail(ctx, HL_E_INVAL, "bad normal arrays");
+    for (int64_t e = 0; e < n_w; ++e)
+        if (site[e] < 0 || site[e] >= d.n) return fail(ctx, HL_E_RANGE, "normal %lld names no site", (long long)e);
+    d.wn_site.assign(site, site + n_w);
+    d.wn.assign(nrm, nrm + 3 * (size_t)n_w);
+    return HL_OK;
+}
+
+int hl_set_wall_mode(hl_ctx *ctx, int32_t dom, int mode) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (mode != HL_WALL_SBB && mode != HL_WALL_BOUZIDI) return fail(ctx, HL_E_INVAL, "unknown wall mode %d", mode);
+    ctx->doms[dom].wall_mode = mode;
+    return upload_params(ctx);
+}
+
+int hl_set_tau(hl_ctx *ctx, int32_t dom, double tau) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (!std::isfinite(tau) || tau <= 0.5) return fail(ctx, HL_E_INVAL, "tau = %g must exceed 1/2", tau);
+    ctx->doms[dom].tau = tau;
+    rc = upload_params(ctx);
+    if (rc) return rc;
+    return tau > 1.0 ? HL_W_TAU : HL_OK;
+}
+
+int hl_set_iolet(hl_ctx *ctx, int32_t dom, int32_t k, int kind, const double centre[3], const double normal[3],
+                 double radius) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (ctx->committed) return fail(ctx, HL_E_STATE, "iolets cannot change after the first step");
+    Domain &d = ctx->doms[dom];
+    if (k < 0 || k >= d.n_iolet) return fail(ctx, HL_E_RANGE, "iolet %d does not exist", k);
+    if (kind != HL_INLET_VEL && kind != HL_OUTLET_P) return fail(ctx, HL_E_INVAL, "unknown iolet kind");
+    if (!centre || !normal) return fail(ctx, HL_E_INVAL, "NULL centre or normal");
+    const double nl = std::sqrt(normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2]);
+    if (!(nl > 0.0) || !(radius > 0.0)) return fail(ctx, HL_E_INVAL, "zero normal or radius");
+    IoletH &io = d.io[k];
+    if (io.coupled && io.kind != kind) return fail(ctx, HL_E_INVAL, "iolet %d is coupled", k);
+    io.kind = kind;
+    for (int a = 0; a < 3; ++a) {
+        io.c[a] = centre[a];
+        io.nrm[a] = normal[a] / nl;
+    }
+    io.R = radius;
+    io.wave = Series{};
+    io.wave.a0 = (kind == HL_OUTLET_P) ? hl::RHO0 : 0.0;
+    return HL_OK;
+}
+
+static int set_series(hl_ctx *ctx, int32_t dom, int32_t k, int kind, double a0, int nh, const double *a,
+                      const double *b, double period) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    Domain &d = ctx->doms[dom];
+    if (k < 0 || k >= d.n_iolet) return fail(ctx, HL_E_RANGE, "iolet %d does not exist", k);
+    if (d.io[k].kind != kind) return fail(ctx, HL_E_INVAL, "iolet %d has the other kind", k);
+    Series s;
+    if ((rc = parse_series(ctx, s, a0, nh, a, b, period)) != HL_OK) return rc;
+    d.io[k].wave = s;
+    if ((rc = refresh_series(ctx, dom, k)) != HL_OK) return rc;
+    if (kind == HL_INLET_VEL && std::sqrt(3.0) * s.bound() >= 0.1) return HL_W_MACH;
+    return HL_OK;
+}
+
+int hl_set_inlet_velocity(hl_ctx *ctx, int32_t dom, int32_t k, double a0, int nh, const double *a, const double *b,
+                          double period) {
+    return set_series(ctx, dom, k, HL_INLET_VEL, a0, nh, a, b, period);
+}
+
+int hl_set_outlet_density(hl_ctx *ctx, int32_t dom, int32_t k, double rho0, int nh, const double *a,
+                          const double *b, double period) {
+    if (ctx && !(rho0 > 0.0)) return fail(ctx, HL_E_INVAL, "outlet density must be positive");
+    return set_series(ctx, dom, k, HL_OUTLET_P, rho0, nh, a, b, period);
+}
+
+int hl_set_body_force(hl_ctx *ctx, int32_t dom, const double F0[3], double omega) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (!F0 || !std::isfinite(F0[0]) || !std::isfinite(F0[1]) || !std::isfinite(F0[2]) || !std::isfinite(omega))
+        return fail(ctx, HL_E_INVAL, "bad body force");
+    for (int a = 0; a < 3; ++a) ctx->doms[dom].F0[a] = F0[a];
+    ctx->doms[dom].omega = omega;
+    return upload_params(ctx);
+}
+
+int hl_couple(hl_ctx *ctx, int32_t dom_a, int32_t outlet, int32_t dom_b, int32_t inlet, double s_vel,
+              double dp_ratio) {
+    int rc;
+    if ((rc = check_dom(ctx, dom_a)) || (rc = check_dom(ctx, dom_b))) return rc;
+    if (ctx->committed) return fail(ctx, HL_E_STATE, "coupling cannot change after the first step");
+    Domain &a = ctx->doms[dom_a], &b = ctx->doms[dom_b];
+    if (outlet < 0 || outlet >= a.n_iolet || inlet < 0 || inlet >= b.n_iolet)
+        return fail(ctx, HL_E_RANGE, "iolet index out of range");
+    if (a.io[outlet].kind != HL_OUTLET_P || b.io[inlet].kind != HL_INLET_VEL)
+        return fail(ctx, HL_E_INVAL, "coupling runs from an outlet to an inlet");
+    if (b.io[inlet].coupled) return fail(ctx, HL_E_INVAL, "inlet already coupled");
+    if (!(dp_ratio > 0.0 && dp_ratio < 1.0) || !std::isfinite(s_vel))
+        return fail(ctx, HL_E_INVAL, "dp_ratio must lie in (0,1)");
+    ctx->pairs.push_back({dom_a, outlet, dom_b, inlet, s_vel, dp_ratio});
+    a.io[outlet].coupled = true;
+    b.io[inlet].coupled = true;
+    return HL_OK;
+}
+
+int hl_set_coupling_mode(hl_ctx *ctx, int mode) {
+    if (!ctx) return HL_E_INVAL;
+    if (ctx->committed) return fail(ctx, HL_E_STATE, "coupling mode cannot change after the first step");
+    if (mode != HL_ALTERNATE && mode != HL_BOTH_EACH_STEP) return fail(ctx, HL_E_INVAL, "unknown coupling mode");
+    ctx->couple_mode = mode;
+    return HL_OK;
+}
+
+int hl_commit(hl_ctx *ctx) {
+    if (!ctx) return HL_E_INVAL;
+    return commit(ctx);
+}
+
+int hl_step(hl_ctx *ctx, int64_t nsteps) {
+    if (!ctx) return HL_E_INVAL;
+    if (nsteps < 0) return fail(ctx, HL_E_INVAL, "nsteps < 0");
+    int rc = commit(ctx);
+    if (rc) return rc;
+    if (*ctx->h_nan) return fail(ctx, HL_E_DIVERGED, "a non-finite density appeared");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    return run_steps(ctx, nsteps);
+}
+
+int hl_sync(hl_ctx *ctx) {
+    if (!ctx) return HL_E_INVAL;
+    if (!ctx->committed) return HL_OK;
+    return read_nan(ctx);
+}
+
+int hl_get_time(hl_ctx *ctx, int64_t *t) {
+    if (!ctx || !t) return HL_E_INVAL;
+    *t = ctx->t_host;
+    return HL_OK;
+}
+
+int hl_set_drive(hl_ctx *ctx, int drive, int32_t steps_per_graph) {
+    if (!ctx) return HL_E_INVAL;
+    if (drive != HL_DRIVE_LAUNCH && drive != HL_DRIVE_GRAPH) return fail(ctx, HL_E_INVAL, "unknown drive");
+    if (drive == HL_DRIVE_GRAPH && steps_per_graph < 1) return fail(ctx, HL_E_INVAL, "steps_per_graph < 1");
+    ctx->drive = drive;
+    if (drive == HL_DRIVE_GRAPH) ctx->steps_per_graph = steps_per_graph;
+    return HL_OK;
+}
+
+static int read_component(hl_ctx *ctx, int32_t dom, int comp, int ncomp, double *out) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (!out) return fail(ctx, HL_E_INVAL, "NULL output");
+    if ((rc = commit(ctx)) != HL_OK) return rc;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    if ((rc = observe(ctx, false)) != HL_OK) return rc;
+    const int64_t N = ctx->N;
+    std::vector<double> buf((size_t)ncomp * N);
+    HIPC(ctx, hipMemcpyAsync(buf.data(), ctx->d_obs + (size_t)comp * N, buf.size() * 8, hipMemcpyDeviceToHost,
+                             ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    const Domain &d = ctx->doms[dom];
+    for (int m = 0; m < ncomp; ++m)
+        for (int64_t x = 0; x < d.n; ++x) out[(size_t)m * d.n + x] = buf[(size_t)m * N + d.c2g[x]];
+    return read_nan(ctx);
+}
+
+int hl_read_density(hl_ctx *ctx, int32_t dom, double *out) { return read_component(ctx, dom, 0, 1, out); }
+int hl_read_velocity(hl_ctx *ctx, int32_t dom, double *out) { return read_component(ctx, dom, 1, 3, out); }
+int hl_read_wss(hl_ctx *ctx, int32_t dom, double *out) { return read_component(ctx, dom, 4, 1, out); }
+
+int hl_read_populations(hl_ctx *ctx, int32_t dom, double *out) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (!out) return fail(ctx, HL_E_INVAL, "NULL output");
+    if ((rc = commit(ctx)) != HL_OK) return rc;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    if ((rc = observe(ctx, true)) != HL_OK) return rc;
+    const int64_t N = ctx->N;
+    std::vector<double> buf((size_t)Q * N);
+    HIPC(ctx, hipMemcpyAsync(buf.data(), ctx->d_fbuf, buf.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    const Domain &d = ctx->doms[dom];
+    for (int i = 0; i < Q; ++i)
+        for (int64_t x = 0; x < d.n; ++x) out[(size_t)i * d.n + x] = buf[(size_t)i * N + d.c2g[x]];
+    return read_nan(ctx);
+}
+
+int hl_set_populations(hl_ctx *ctx, int32_t dom, const double *f) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (!f) return fail(ctx, HL_E_INVAL, "NULL populations");
+    if ((rc = commit(ctx)) != HL_OK) return rc;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    if ((rc = observe(ctx, true)) != HL_OK) return rc;
+    const int64_t N = ctx->N;
+    std::vector<double> buf((size_t)Q * N);
+    HIPC(ctx, hipMemcpyAsync(buf.data(), ctx->d_fbuf, buf.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    const Domain &d = ctx->doms[dom];
+    for (int i = 0; i < Q; ++i)
+        for (int64_t x = 0; x < d.n; ++x) buf[(size_t)i * N + d.c2g[x]] = f[(size_t)i * d.n + x];
+    HIPC(ctx, hipMemcpy(ctx->d_fbuf, buf.data(), buf.size() * 8, hipMemcpyHostToDevice));
+    int zero = 0;
+    HIPC(ctx, hipMemcpy(&ctx->d_ctrl->nan_flag, &zero, sizeof zero, hipMemcpyHostToDevice));
+    *ctx->h_nan = 0;
+    hl::KArgs a = make_args(ctx);
+    a.fin = ctx->d_fbuf;
+    int e = hl::launch_load_raw(ctx->precision, a, ctx->stream);
+    if (e != 0) return fail(ctx, HL_E_DEVICE, "load launch failed: %s", hipGetErrorString((hipError_t)e));
+    if ((rc = reinit(ctx)) != HL_OK) return rc;
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    return HL_OK;
+}
+
+int hl_read_iolet_stats(hl_ctx *ctx, int32_t dom, double *mean_u, double *mean_p) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if ((rc = commit(ctx)) != HL_OK) return rc;
+    const Domain &d = ctx->doms[dom];
+    if (d.n_iolet == 0) return HL_OK;
+    if (!mean_u || !mean_p) return fail(ctx, HL_E_INVAL, "NULL output");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    const size_t nio = ctx->hio.size();
+    std::vector<double> st(2 * nio);
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    HIPC(ctx, hipMemcpy(st.data(), ctx->d_stats, st.size() * 8, hipMemcpyDeviceToHost));
+    for (int k = 0; k < d.n_iolet; ++k) {
+        mean_u[k] = st[d.io_base + k];
+        mean_p[k] = (st[nio + d.io_base + k] - hl::RHO0) / 3.0;
+    }
+    return read_nan(ctx);
+}
+
+int hl_read_iolet_bc(hl_ctx *ctx, int32_t dom, int which, double *out) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (which != 0 && which != 1) return fail(ctx, HL_E_INVAL, "which must be 0 or 1");
+    if ((rc = commit(ctx)) != HL_OK) return rc;
+    if (which == 1 && ctx->t_host == 0) return fail(ctx, HL_E_STATE, "no step has been taken");
+    const Domain &d = ctx->doms[dom];
+    if (d.n_iolet == 0) return HL_OK;
+    if (!out) return fail(ctx, HL_E_INVAL, "NULL output");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    const size_t nio = ctx->hio.size();
+    std::vector<double> bc(2 * nio);
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    HIPC(ctx, hipMemcpy(bc.data(), ctx->d_bc, bc.size() * 8, hipMemcpyDeviceToHost));
+    const int64_t par = (ctx->t_host - which) & 1;
+    for (int k = 0; k < d.n_iolet; ++k) out[k] = bc[par * nio + d.io_base + k];
+    return read_nan(ctx);
+}
+
+static int read_device(hl_ctx *ctx, int32_t dom, int comp, int ncomp, void *dptr) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (!dptr) return fail(ctx, HL_E_INVAL, "NULL device pointer");
+    if ((rc = commit(ctx)) != HL_OK) return rc;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    if ((rc = observe(ctx, false)) != HL_OK) return rc;
+    Domain &d = ctx->doms[dom];
+    if (!d.d_c2g) {
+        if ((rc = dalloc(ctx, &d.d_c2g, d.n)) != HL_OK) return rc;
+        HIPC(ctx, hipMemcpy(d.d_c2g, d.c2g.data(), d.n * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    for (int m = 0; m < ncomp; ++m) {
+        int e = hl::launch_gather_obs(ctx->d_obs + (size_t)(comp + m) * ctx->N, d.d_c2g, d.n,
+                                      (double *)dptr + (size_t)m * d.n, ctx->stream);
+        if (e != 0) return fail(ctx, HL_E_DEVICE, "gather launch failed");
+    }
+    return HL_OK;
+}
+
+int hl_read_density_device(hl_ctx *ctx, int32_t dom, void *dptr) { return read_device(ctx, dom, 0, 1, dptr); }
+int hl_read_velocity_device(hl_ctx *ctx, int32_t dom, void *dptr) { return read_device(ctx, dom, 1, 3, dptr); }
+int hl_read_wss_device(hl_ctx *ctx, int32_t dom, void *dptr) { return read_device(ctx, dom, 4, 1, dptr); }
+
+int hl_get_state(hl_ctx *ctx, void *buf, size_t *bytes) {
+    if (!ctx || !bytes) return HL_E_INVAL;
+    int rc = commit(ctx);
+    if (rc) return rc;
+    const size_t need = state_bytes(ctx);
+    if (!buf) {
+        *bytes = need;
+        return HL_OK;
+    }
+    if (*bytes < need) return fail(ctx, HL_E_INVAL, "state buffer holds %zu of %zu bytes", *bytes, need);
+    *bytes = need;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    char *p = (char *)buf;
+    StateHeader h{};
+    std::memcpy(h.magic, "HLSTATE", 8);
+    h.version = 1;
+    h.precision = ctx->precision;
+    h.N = ctx->N;
+    h.Nio = ctx->Nio;
+    h.n_io = (int64_t)ctx->hio.size();
+    h.bytes = (int64_t)need;
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    const size_t S = store_bytes(ctx->precision), A = arith_bytes(ctx->precision), nio = ctx->hio.size();
+    HIPC(ctx, hipMemcpy(p, ctx->d_ctrl, sizeof(hl::Ctrl), hipMemcpyDeviceToHost));
+    p += sizeof(hl::Ctrl);
+    for (int k = 0; k < 2; ++k) {
+        HIPC(ctx, hipMemcpy(p, ctx->lat[k], (size_t)Q * ctx->N * S, hipMemcpyDeviceToHost));
+        p += (size_t)Q * ctx->N * S;
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (ctx->Nio) HIPC(ctx, hipMemcpy(p, ctx->d_up[k], (size_t)3 * ctx->Nio * A, hipMemcpyDeviceToHost));
+        p += (size_t)3 * ctx->Nio * A;
+    }
+    if (nio) {
+        HIPC(ctx, hipMemcpy(p, ctx->d_stats, 2 * nio * 8, hipMemcpyDeviceToHost));
+        HIPC(ctx, hipMemcpy(p + 2 * nio * 8, ctx->d_bc, 2 * nio * 8, hipMemcpyDeviceToHost));
+        HIPC(ctx, hipMemcpy(p + 4 * nio * 8, ctx->d_held, nio * 8, hipMemcpyDeviceToHost));
+    }
+    return HL_OK;
+}
+
+int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes) {
+    if (!ctx || !buf) return HL_E_INVAL;
+    int rc = commit(ctx);
+    if (rc) return rc;
+    const size_t need = state_bytes(ctx);
+    StateHeader h;
+    if (bytes < sizeof h) return fail(ctx, HL_E_INVAL, "state too short");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, "HLSTATE", 8) != 0 || h.version != 1)
+        return fail(ctx, HL_E_INVAL, "not a state buffer of this library version");
+    if (bytes != need || h.bytes != (int64_t)need || h.precision != ctx->precision || h.N != ctx->N ||
+        h.Nio != ctx->Nio || h.n_io != (int64_t)ctx->hio.size())
+        return fail(ctx, HL_E_INVAL, "state layout does not match this context");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    const char *p = (const char *)buf + sizeof h;
+    const size_t S = store_bytes(ctx->precision), A = arith_bytes(ctx->precision), nio = ctx->hio.size();
+    hl::Ctrl ctrl;
+    std::memcpy(&ctrl, p, sizeof ctrl);
+    HIPC(ctx, hipMemcpy(ctx->d_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
+    p += sizeof(hl::Ctrl);
+    for (int k = 0; k < 2; ++k) {
+        HIPC(ctx, hipMemcpy(ctx->lat[k], p, (size_t)Q * ctx->N * S, hipMemcpyHostToDevice));
+        p += (size_t)Q * ctx->N * S;
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (ctx->Nio) HIPC(ctx, hipMemcpy(ctx->d_up[k], p, (size_t)3 * ctx->Nio * A, hipMemcpyHostToDevice));
+        p += (size_t)3 * ctx->Nio * A;
+    }
+    if (nio) {
+        HIPC(ctx, hipMemcpy(ctx->d_stats, p, 2 * nio * 8, hipMemcpyHostToDevice));
+        HIPC(ctx, hipMemcpy(ctx->d_bc, p + 2 * nio * 8, 2 * nio * 8, hipMemcpyHostToDevice));
+        HIPC(ctx, hipMemcpy(ctx->d_held, p + 4 * nio * 8, nio * 8, hipMemcpyHostToDevice));
+    }
+    ctx->t_host = ctrl.t;
+    *ctx->h_nan = ctrl.nan_flag;
+    ctx->obs_t = -1;
+    return HL_OK;
+}
+
+int hl_get_schedule(hl_ctx *ctx, int32_t *block_size, int32_t *flags) {
+    if (!ctx || !block_size || !flags) return HL_E_INVAL;
+    *block_size = ctx->block;
+    *flags = ctx->sched_flags;
+    return HL_OK;
+}
+
+int hl_set_schedule(hl_ctx *ctx, int32_t block_size, int32_t flags) {
+    if (!ctx) return HL_E_INVAL;
+    if (block_size != 64 && block_size != 128 && block_size != 256)
+        return fail(ctx, HL_E_INVAL, "block size %d not in {64, 128, 256}", block_size);
+    if (flags & ~(int32_t)HL_SCHED_XCD_REMAP) return fail(ctx, HL_E_INVAL, "unknown schedule flags");
+    const bool rebuild = block_size != ctx->block;
+    ctx->block = block_size;
+    ctx->sched_flags = flags;
+    if (!ctx->committed) return HL_OK;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    if (rebuild) {
+        build_entries(ctx);
+        return upload_schedule(ctx);
+    }
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+    ctx->graph_steps = 0;
+    return HL_OK;
+}
+
+int hl_autotune(hl_ctx *ctx, int budget_ms) {
+    if (!ctx) return HL_E_INVAL;
+    if (budget_ms < 1) return fail(ctx, HL_E_INVAL, "budget must be positive");
+    int rc = commit(ctx);
+    if (rc) return rc;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    size_t bytes = 0;
+    if ((rc = hl_get_state(ctx, nullptr, &bytes)) != HL_OK) return rc;
+    std::vector<char> saved(bytes);
+    if ((rc = hl_get_state(ctx, saved.data(), &bytes)) != HL_OK) return rc;
+    const int drive = ctx->drive;
+    ctx->drive = HL_DRIVE_LAUNCH;
+    struct Cand { int block, flags; double ms; };
+    std::vector<Cand> cands;
+    for (int b : {64, 128, 256})
+        for (int f : {0, (int)HL_SCHED_XCD_REMAP}) cands.push_back({b, f, 0.0});
+    hipEvent_t e0, e1;
+    HIPC(ctx, hipEventCreate(&e0));
+    HIPC(ctx, hipEventCreate(&e1));
+    // steps per candidate from one timed step of the current schedule
+    int64_t reps = 2;
+    {
+        if ((rc = run_steps(ctx, 1)) != HL_OK) return rc;
+        HIPC(ctx, hipEventRecord(e0, ctx->stream));
+        if ((rc = run_steps(ctx, 2)) != HL_OK) return rc;
+        HIPC(ctx, hipEventRecord(e1, ctx->stream));
+        HIPC(ctx, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
+        const double per = std::max(1e-3, (double)ms / 2.0);
+        reps = std::max<int64_t>(2, (int64_t)((double)budget_ms / (per * (double)cands.size())));
+        reps = std::min<int64_t>(reps, 200);
+    }
+    for (auto &cd : cands) {
+        if ((rc = hl_set_schedule(ctx, cd.block, cd.flags)) != HL_OK) return rc;
+        if ((rc = run_steps(ctx, 1)) != HL_OK) return rc;
+        HIPC(ctx, hipEventRecord(e0, ctx->stream));
+        if ((rc = run_steps(ctx, reps)) != HL_OK) return rc;
+        HIPC(ctx, hipEventRecord(e1, ctx->stream));
+        HIPC(ctx, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
+        cd.ms = (double)ms / (double)reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const Cand best = *std::min_element(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
+    if ((rc = hl_set_schedule(ctx, best.block, best.flags)) != HL_OK) return rc;
+    ctx->drive = drive;
+    return hl_set_state(ctx, saved.data(), saved.size());
+}
+
+int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd) {
+    if (!ctx || !ms_bulk || !ms_bnd) return HL_E_INVAL;
+    if (nsteps < 1 || nsteps > 100000) return fail(ctx, HL_E_INVAL, "nsteps must lie in 1..100000");
+    int rc = commit(ctx);
+    if (rc) return rc;
+    if (*ctx->h_nan) return fail(ctx, HL_E_DIVERGED, "a non-finite density appeared");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    std::vector<hipEvent_t> ev((size_t)3 * nsteps, nullptr);
+    for (auto &e : ev) HIPC(ctx, hipEventCreate(&e));
+    const hl::KArgs a = make_args(ctx);
+    int err = 0;
+    for (int64_t k = 0; k < nsteps && !err; ++k) {
+        HIPC(ctx, hipEventRecord(ev[3 * k], ctx->stream));
+        err = hl::launch_step(ctx->precision, a, ctx->n_bulk_blocks, ctx->n_bnd_blocks, ctx->block, ctx->stream, 1);
+        HIPC(ctx, hipEventRecord(ev[3 * k + 1], ctx->stream));
+        if (!err)
+            err = hl::launch_step(ctx->precision, a, ctx->n_bulk_blocks, ctx->n_bnd_blocks, ctx->block, ctx->stream, 2);
+        HIPC(ctx, hipEventRecord(ev[3 * k + 2], ctx->stream));
+    }
+    HIPC(ctx, hipEventSynchronize(ev.back()));
+    double sb = 0.0, sn = 0.0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        float m1 = 0.0f, m2 = 0.0f;
+        HIPC(ctx, hipEventElapsedTime(&m1, ev[3 * k], ev[3 * k + 1]));
+        HIPC(ctx, hipEventElapsedTime(&m2, ev[3 * k + 1], ev[3 * k + 2]));
+        sb += m1;
+        sn += m2;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (err) return fail(ctx, HL_E_DEVICE, "step launch failed: %s", hipGetErrorString((hipError_t)err));
+    ctx->t_host += nsteps;
+    ctx->obs_t = -1;
+    *ms_bulk = sb / (double)nsteps;
+    *ms_bnd = sn / (double)nsteps;
+    return HL_OK;
+}
+
+int hl_get_info(hl_ctx *ctx, hl_info *out) {
+    if (!ctx || !out) return HL_E_INVAL;
+    int rc = commit(ctx);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof *out);
+    out->n_sites = ctx->N;
+    out->n_bulk = ctx->NB;
+    out->n_boundary = ctx->Nb;
+    out->n_iolet_sites = ctx->Nio;
+    out->n_domains = (int32_t)ctx->doms.size();
+    out->n_iolets = (int32_t)ctx->hio.size();
+    out->n_blocks_bulk = ctx->n_bulk_blocks;
+    out->n_blocks_bnd = ctx->n_bnd_blocks;
+    out->precision = ctx->precision;
+    out->block_size = ctx->block;
+    out->sched_flags = ctx->sched_flags;
+    out->drive = ctx->drive;
+    out->device_bytes = ctx->dev_bytes;
+    out->bytes_per_site = 2.0 * Q * (double)store_bytes(ctx->precision) + 18.0 * 4.0;
+    return HL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal layout shared by the host driver (hl_api.cpp) and the gfx950
+// kernels (hl_kernels.hip).  Nothing here is part of the public C ABI.
+//
+// Device layout of a committed context (all domains concatenated):
+//   sites      internal order: bulk sites of every domain, then wall-only
+//              boundary sites per domain, then the sites bordering each
+//              iolet, grouped by global iolet id.
+//   lat[2]     populations, structure of arrays [19][N]; FP64 holds f_i,
+//              FP32/FP16 hold the offset g_i = f_i - w_i rho0.  lat[t&1]
+//              holds the post-collision state f*(t); lat[(t+1)&1] holds
+//              f*(t-1), or the raw f(t) right after a (re)initialisation.
+//   src        int32 [18][N] pull table: src[j-1][s] is the internal index of
+//              the site at x_s - c_j, or -1 (wall link) / -2-g (iolet g).
+//   bq         float [18][Nb] wall fraction q of the link (s, opp(j)).
+//   bphi       double [Nb] inlet profile factor max(0, 1 - r^2/R^2).
+//   bnrm       double [3][Nb] unit wall normal (0 for sites without walls).
+//   uprev[2]   [3][Nio] velocity of each iolet site at step t (parity t&1).
+#pragma once
+#include <stdint.h>
+
+namespace hl {
+
+constexpr int Q = 19;
+constexpr int MAXH = 8;
+constexpr double RHO0 = 1.0;
+
+enum : int32_t { K_BULK = 0, K_WALL = 1, K_IOLET = 2 };
+enum : int32_t { KIND_INLET = 0, KIND_OUTLET = 1 };
+enum : int32_t { WALL_SBB = 0, WALL_BOUZIDI = 1 };
+enum : int32_t { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1 };
+enum : int32_t { PREC_F64 = 0, PREC_F32 = 1, PREC_F16 = 2 };
+
+// One work-group's share of sites: a contiguous internal range inside one
+// domain and one class.  tag = class | (global iolet id << 2).
+struct Entry {
+    int32_t start;
+    int32_t count;
+    int32_t seg;
+    int32_t tag;
+};
+
+// Per-domain constants read uniformly by a work-group.
+struct SegDev {
+    double inv_tau;    // 1/tau
+    double guo_pref;   // 1 - 1/(2 tau)
+    double F0[3];      // body force amplitude
+    double omega;      // body force angular frequency
+    int32_t wall_mode;
+    int32_t has_force;
+};
+
+struct IoletDev {
+    double nrm[3];     // unit normal (into the fluid for inlets, out for outlets)
+    double area;       // number of bordering sites
+    double phibar;     // mean inlet profile factor over those sites
+    double a0, a[MAXH], b[MAXH], period;
+    int32_t nh, kind, coupled, seg;
+    int32_t e_lo, e_hi;       // schedule entries covering the iolet's sites
+    int32_t pair_lo, pair_n;  // coupling pairs whose arterial outlet is this iolet
+};
+
+struct PairDev {
+    int32_t out_g, in_g;
+    double s, delta;
+};
+
+struct Ctrl {
+    int64_t t;          // step of the stored state
+    int32_t direct;     // 1: lat[(t+1)&1] holds raw f(t)
+    int32_t nan_flag;   // sticky non-finite density flag
+};
+
+struct KArgs {
+    int64_t N, NB, IO0, Nb, Nio;
+    void *lat0, *lat1;
+    const int32_t *src;
+    const float *bq;
+    const double *bphi;
+    void *up0, *up1;
+    const double *bnrm;
+    const Entry *entries;
+    int32_t e_off;           // first entry of this launch
+    const SegDev *seg;
+    const IoletDev *io;
+    const PairDev *pairs;
+    int32_t n_io, n_pairs;
+    int32_t couple_mode, xcd_remap;
+    Ctrl *ctrl;
+    double *partials;  // [2][n_entries]
+    double *stats;     // [2][n_io]: mean u.n, mean rho
+    double *bc;        // [2][n_io] boundary values by step parity
+    double *held;      // [n_io] held coupled values
+    double *obs;       // [5][N] rho, ux, uy, uz, wss
+    double *fout;      // [19][N] full f(t) or null
+    const double *fin; // [19][N] full f(t) to load
+};
+
+// Kernel launchers (hl_kernels.hip).  Each returns a hipError_t value.
+// part: 0 = every launch of a step, 1 = the bulk-site launch only, 2 = the
+// boundary-site launch and the finalize only.
+int launch_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part = 0);
+int launch_init(int prec, const KArgs &a, int n_entries, int block, void *stream);
+int launch_observe(int prec, const KArgs &a, int n_entries, int block, void *stream);
+int launch_load_raw(int prec, const KArgs &a, void *stream);
+int launch_fill_rest(int prec, const KArgs &a, void *stream);
+int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *out, void *stream);
+
+}  // namespace hl

@@ -1,0 +1,552 @@
+// gfx950 kernels of the sparse D3Q19 LBGK step.
+//
+// One lane owns one fluid site.  A step t -> t+1 is the fused pull form of
+// the stream-and-collide update (Sec. 2 of the paper: D3Q19, single
+// relaxation time, rigid walls, velocity and pressure boundaries):
+//   1. gather f_j(x, t+1) = f*_j(x - c_j, t) through the int32 pull table,
+//   2. replace the populations whose upstream voxel is not fluid by the
+//      boundary rule of that link (halfway or Bouzidi wall, Ladd velocity
+//      inlet, equilibrium pressure outlet),
+//   3. take the moments, relax toward the second-order equilibrium with
+//      Guo's forcing term, and store f*(t+1) to the other lattice.
+// Work-groups whose sites border an iolet also reduce (in FP64, in a fixed
+// order) the mean velocity along the iolet normal and the mean density; a
+// one-work-group kernel queued after them turns those means into the
+// boundary values of the next step, including the arterial-venous coupling
+// of Sec. 2.3 and Sec. 3 (forward on even steps, reverse on odd steps,
+// Eq. (1)-(2)).  Stream order alone separates the kernels of a step: no
+// device-wide fences or atomics are needed.
+//
+// The lattice is bandwidth-bound (about 1 flop per byte), so there is no
+// matrix-core work here: the design goal is coalesced SoA traffic.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include "hl_internal.h"
+
+namespace hl {
+
+// Velocity set of the site-list interface (rest, faces, edges; opposite
+// directions adjacent).
+static constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+template <typename R>
+__device__ __forceinline__ constexpr R wgt(int i) {
+    return i == 0 ? R(1.0) / R(3.0) : (i <= 6 ? R(1.0) / R(18.0) : R(1.0) / R(36.0));
+}
+
+// Storage type -> arithmetic type.  FP64 stores f, FP32/FP16 store offsets.
+template <typename T> struct Arith { using R = float; static constexpr bool OFF = true; };
+template <> struct Arith<double> { using R = double; static constexpr bool OFF = false; };
+
+__device__ __forceinline__ double ldc(const double *p) { return *p; }
+__device__ __forceinline__ float ldc(const float *p) { return *p; }
+__device__ __forceinline__ float ldc(const __half *p) { return __half2float(*p); }
+__device__ __forceinline__ void stc(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void stc(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void stc(__half *p, float v) { *p = __float2half_rn(v); }
+
+template <typename T>
+__device__ __forceinline__ const T *lat_ptr(const KArgs &a, int64_t parity) {
+    return (const T *)((parity & 1) ? a.lat1 : a.lat0);
+}
+
+// XCD-aware order: work-group b runs on XCD b % 8; hand each XCD a
+// contiguous range of entries so neighbouring sites share an L2.
+__device__ __forceinline__ int block_index(int xcd_remap) {
+    const int b = blockIdx.x;
+    if (!xcd_remap) return b;
+    const int G = gridDim.x;
+    const int per = G >> 3, rem = G & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+// ---------------------------------------------------------------------------
+// Step 1-2: the populations f_j(x, p+1) of site s, streamed from f*(p).
+// BND selects the boundary path (pull codes may be negative).
+// ---------------------------------------------------------------------------
+template <typename T, bool BND>
+__device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const SegDev &sg, int64_t p,
+                                       int64_t s, typename Arith<T>::R (&x)[Q]) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    const T *__restrict__ lin = lat_ptr<T>(a, p);
+    const int64_t N = a.N;
+    int32_t sr[Q];
+#pragma unroll
+    for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+    x[0] = ldc(lin + s);
+#pragma unroll
+    for (int j = 1; j < Q; ++j) {
+        if (BND)
+            x[j] = (sr[j] >= 0) ? ldc(lin + (size_t)j * N + sr[j]) : R(0);
+        else
+            x[j] = ldc(lin + (size_t)j * N + sr[j]);
+    }
+    if (!BND) return;
+
+    const int64_t b = s - a.NB;
+    const int klass = e.tag & 3;
+    int kind = KIND_INLET;
+    R U = 0, nx = 0, ny = 0, nz = 0, phi = 0;
+    R rho_out = 0, drho_out = 0, ux = 0, uy = 0, uz = 0;
+    if (klass == K_IOLET) {
+        const int g = e.tag >> 2;
+        const IoletDev &io = a.io[g];
+        kind = io.kind;
+        const double v = a.bc[(p & 1) * a.n_io + g];
+        if (kind == KIND_INLET) {
+            U = (R)v;
+            nx = (R)io.nrm[0];
+            ny = (R)io.nrm[1];
+            nz = (R)io.nrm[2];
+            phi = (R)a.bphi[b];
+        } else {
+            rho_out = (R)v;
+            drho_out = (R)(v - RHO0);
+            const R *up = (const R *)((p & 1) ? a.up1 : a.up0);
+            const int64_t vi = s - a.IO0;
+            ux = up[vi];
+            uy = up[a.Nio + vi];
+            uz = up[2 * a.Nio + vi];
+        }
+    }
+#pragma unroll
+    for (int j = 1; j < Q; ++j) {
+        if (sr[j] >= 0) continue;
+        const int jb = opp(j);
+        if (sr[j] == -1) {
+            // wall link (s, jb): the wall lies at x_s + q c_jb
+            const R own_opp = ldc(lin + (size_t)jb * N + s);  // f*_jb(s)
+            if (sg.wall_mode == WALL_BOUZIDI) {
+                const R q = (R)a.bq[(size_t)(j - 1) * a.Nb + b];
+                if (q < R(0.5)) {
+                    // second node x_s - c_jb = x_s + c_j, pulled as x[jb]
+                    x[j] = (sr[jb] >= 0) ? R(2) * q * own_opp + (R(1) - R(2) * q) * x[jb] : own_opp;
+                } else {
+                    const R own = ldc(lin + (size_t)j * N + s);  // f*_j(s)
+                    x[j] = own_opp / (R(2) * q) + (R(1) - R(1) / (R(2) * q)) * own;
+                }
+            } else {
+                x[j] = own_opp;
+            }
+        } else if (kind == KIND_INLET) {
+            // Ladd: f_j = f*_jb - 6 w rho0 (c_jb . u_w), u_w = U phi n
+            const R own_opp = ldc(lin + (size_t)jb * N + s);
+            const R cn = R(CX[jb]) * nx + R(CY[jb]) * ny + R(CZ[jb]) * nz;
+            x[j] = own_opp - R(6) * wgt<R>(j) * R(RHO0) * (cn * (U * phi));
+        } else {
+            // pressure outlet: equilibrium at rho_out and the site's velocity
+            const R cu = R(CX[j]) * ux + R(CY[j]) * uy + R(CZ[j]) * uz;
+            const R uu = ux * ux + uy * uy + uz * uz;
+            const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+            if (OFF)
+                x[j] = wgt<R>(j) * (drho_out + rho_out * poly);
+            else
+                x[j] = wgt<R>(j) * rho_out * (R(1) + poly);
+        }
+    }
+}
+
+// Deterministic FP64 sum over the work-group; the result is valid in lane 0
+// of wave 0.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) r += lds[w];
+    }
+    __syncthreads();
+    return r;
+}
+
+__device__ double series_at(const IoletDev &io, int64_t t) {
+    double v = io.a0;
+    for (int m = 1; m <= io.nh; ++m) {
+        const double ph = 2.0 * M_PI * (double)m * (double)t / io.period;
+        v = v + io.a[m - 1] * cos(ph) + io.b[m - 1] * sin(ph);
+    }
+    return v;
+}
+
+// One work-group after the site kernels of a step (stream order, no
+// fences): iolet means of f(tn) from the per-work-group partial sums,
+// coupling, boundary values for the stream tn -> tn+1, then publish tn.
+// raw = 1 after a (re)initialisation, where tn = t.
+__global__ void __launch_bounds__(256) k_finalize(KArgs a, int raw) {
+    const int64_t t = a.ctrl->t;
+    const int64_t tn = raw ? t : t + 1;
+    double *mu = a.stats;
+    double *mr = a.stats + a.n_io;
+    for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
+        const IoletDev &io = a.io[k];
+        double su = 0.0, sr = 0.0;
+        for (int e = io.e_lo; e < io.e_hi; ++e) {
+            su = su + a.partials[2 * e];
+            sr = sr + a.partials[2 * e + 1];
+        }
+        mu[k] = io.area > 0.0 ? su / io.area : 0.0;
+        mr[k] = io.area > 0.0 ? sr / io.area : RHO0;
+        if (!isfinite(su) || !isfinite(sr)) a.ctrl->nan_flag = 1;
+    }
+    __syncthreads();
+    const bool fwd = a.couple_mode == COUPLE_BOTH || (tn % 2 == 0);
+    const bool rev = a.couple_mode == COUPLE_BOTH || (tn % 2 == 1);
+    if (fwd) {
+        for (int p = threadIdx.x; p < a.n_pairs; p += blockDim.x) {
+            const PairDev pr = a.pairs[p];
+            const double pb = a.io[pr.in_g].phibar;
+            a.held[pr.in_g] = pb > 0.0 ? pr.s * mu[pr.out_g] / pb : 0.0;
+        }
+    }
+    if (rev) {
+        for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
+            const IoletDev &io = a.io[k];
+            if (io.pair_n == 0) continue;
+            double sum = 0.0;
+            for (int p = io.pair_lo; p < io.pair_lo + io.pair_n; ++p) {
+                const PairDev pr = a.pairs[p];
+                const double pv = (mr[pr.in_g] - RHO0) / 3.0;
+                sum = sum + pv / (1.0 - pr.delta);
+            }
+            a.held[k] = RHO0 + 3.0 * (sum / (double)io.pair_n);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
+        const IoletDev &io = a.io[k];
+        a.bc[(tn & 1) * a.n_io + k] = io.coupled ? a.held[k] : series_at(io, tn);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.ctrl->direct = raw;
+        a.ctrl->t = tn;
+    }
+}
+
+enum { M_BULK = 0, M_BND = 1, M_RAW = 2 };
+
+// ---------------------------------------------------------------------------
+// The step kernel.  M_BULK / M_BND: pull step t -> t+1 over bulk or boundary
+// entries.  M_RAW: collide the raw f(t) held in lat[(t+1)&1] into lat[t&1]
+// (initialisation and population loads), without advancing t.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_step(KArgs a) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    __shared__ double lds[8];
+    const int64_t t = a.ctrl->t;
+    const int64_t tn = (MODE == M_RAW) ? t : t + 1;
+    const int eidx = a.e_off + block_index(a.xcd_remap);
+    const Entry e = a.entries[eidx];
+    const int klass = e.tag & 3;
+    const SegDev &sg = a.seg[e.seg];
+    const int tid = threadIdx.x;
+    const bool act = tid < e.count;
+    const int64_t s = (int64_t)e.start + tid;
+    const int64_t N = a.N;
+
+    R x[Q];
+    if (act) {
+        if (MODE == M_RAW) {
+            const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s);
+        } else {
+            gather<T, MODE == M_BND>(a, e, sg, t, s, x);
+        }
+    }
+
+    // moments of f(tn)
+    R Fx = 0, Fy = 0, Fz = 0;
+    if (sg.has_force) {
+        const double c = cos(sg.omega * (double)tn);
+        Fx = (R)(sg.F0[0] * c);
+        Fy = (R)(sg.F0[1] * c);
+        Fz = (R)(sg.F0[2] * c);
+    }
+    R rho = 0, drho = 0, ux = 0, uy = 0, uz = 0;
+    bool bad = false;
+    if (act) {
+        R m0 = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            m0 += x[i];
+            if (CX[i]) jx += R(CX[i]) * x[i];
+            if (CY[i]) jy += R(CY[i]) * x[i];
+            if (CZ[i]) jz += R(CZ[i]) * x[i];
+        }
+        if (OFF) {
+            drho = m0;
+            rho = R(RHO0) + drho;
+        } else {
+            rho = m0;
+        }
+        ux = (jx + R(0.5) * Fx) / rho;
+        uy = (jy + R(0.5) * Fy) / rho;
+        uz = (jz + R(0.5) * Fz) / rho;
+        bad = !isfinite(rho);
+
+        if (klass == K_IOLET) {
+            R *up = (R *)((tn & 1) ? a.up1 : a.up0);
+            const int64_t vi = s - a.IO0;
+            up[vi] = ux;
+            up[a.Nio + vi] = uy;
+            up[2 * a.Nio + vi] = uz;
+        }
+
+        // LBGK collision with Guo forcing
+        const R it = (R)sg.inv_tau;
+        const R uu = ux * ux + uy * uy + uz * uz;
+        T *__restrict__ lout = (T *)((tn & 1) ? a.lat1 : a.lat0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+            const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+            const R eq = OFF ? wgt<R>(i) * (drho + rho * poly) : wgt<R>(i) * rho * (R(1) + poly);
+            R o = x[i] - (x[i] - eq) * it;
+            if (sg.has_force) {
+                const R sF = (R(3) * (R(CX[i]) - ux) + R(9) * cu * R(CX[i])) * Fx +
+                             (R(3) * (R(CY[i]) - uy) + R(9) * cu * R(CY[i])) * Fy +
+                             (R(3) * (R(CZ[i]) - uz) + R(9) * cu * R(CZ[i])) * Fz;
+                o += (R)sg.guo_pref * wgt<R>(i) * sF;
+            }
+            stc(lout + (size_t)i * N + s, o);
+        }
+    }
+    if (__ballot(bad) != 0 && (tid & 63) == 0) a.ctrl->nan_flag = 1;
+
+    if (klass == K_IOLET) {
+        const IoletDev &io = a.io[e.tag >> 2];
+        double un = 0.0, rh = 0.0;
+        if (act) {
+            un = (double)ux * io.nrm[0] + (double)uy * io.nrm[1] + (double)uz * io.nrm[2];
+            rh = (double)rho;
+        }
+        const double su = block_sum(un, lds);
+        const double sr = block_sum(rh, lds);
+        if (tid == 0) {
+            a.partials[2 * eidx] = su;
+            a.partials[2 * eidx + 1] = sr;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Observables of f(t): density, velocity, wall shear stress (FP64), and
+// optionally the full populations.  f(t) is re-streamed from f*(t-1) with
+// the boundary values of step t-1, or read directly after a reload.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_observe(KArgs a) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    const int64_t t = a.ctrl->t;
+    const int direct = a.ctrl->direct;
+    const Entry e = a.entries[blockIdx.x];
+    const SegDev &sg = a.seg[e.seg];
+    if ((int)threadIdx.x >= e.count) return;
+    const int64_t s = (int64_t)e.start + threadIdx.x;
+    const int64_t N = a.N;
+    R x[Q];
+    if (direct) {
+        const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s);
+    } else {
+        gather<T, true>(a, e, sg, t - 1, s, x);
+    }
+    double f[Q];
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        f[i] = (double)x[i] + (OFF ? wgt<double>(i) * RHO0 : 0.0);
+        rho += f[i];
+        jx += CX[i] * f[i];
+        jy += CY[i] * f[i];
+        jz += CZ[i] * f[i];
+    }
+    double F[3] = {0.0, 0.0, 0.0};
+    if (sg.has_force) {
+        const double c = cos(sg.omega * (double)t);
+        for (int d = 0; d < 3; ++d) F[d] = sg.F0[d] * c;
+    }
+    const double ux = (jx + 0.5 * F[0]) / rho;
+    const double uy = (jy + 0.5 * F[1]) / rho;
+    const double uz = (jz + 0.5 * F[2]) / rho;
+    double wss = 0.0;
+    const int64_t b = s - a.NB;
+    if (b >= 0) {
+        const double n0 = a.bnrm[b], n1 = a.bnrm[a.Nb + b], n2 = a.bnrm[2 * a.Nb + b];
+        if (n0 != 0.0 || n1 != 0.0 || n2 != 0.0) {
+            const double uu = ux * ux + uy * uy + uz * uz;
+            double P[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+                const double fe = wgt<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+                const double ne = f[i] - fe;
+                const double c3[3] = {(double)CX[i], (double)CY[i], (double)CZ[i]};
+                for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q < 3; ++q) P[p][q] += ne * c3[p] * c3[q];
+            }
+            const double pref = -sg.guo_pref;
+            const double nv[3] = {n0, n1, n2};
+            double tr[3];
+            for (int p = 0; p < 3; ++p) tr[p] = pref * (P[p][0] * nv[0] + P[p][1] * nv[1] + P[p][2] * nv[2]);
+            const double tn = tr[0] * nv[0] + tr[1] * nv[1] + tr[2] * nv[2];
+            const double sx = tr[0] - tn * nv[0], sy = tr[1] - tn * nv[1], sz = tr[2] - tn * nv[2];
+            wss = sqrt(sx * sx + sy * sy + sz * sz);
+        }
+    }
+    a.obs[s] = rho;
+    a.obs[N + s] = ux;
+    a.obs[2 * N + s] = uy;
+    a.obs[3 * N + s] = uz;
+    a.obs[4 * N + s] = wss;
+    if (a.fout) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) a.fout[(size_t)i * N + s] = f[i];
+    }
+}
+
+// Full f(t) (double) -> raw storage in lat[(t+1)&1].
+template <typename T>
+__global__ void k_load_raw(KArgs a) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    const int64_t t = a.ctrl->t;
+    T *raw = (T *)(((t + 1) & 1) ? a.lat1 : a.lat0);
+    const int64_t total = (int64_t)Q * a.N;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / a.N);
+        const double v = a.fin[k] - (OFF ? wgt<double>(i) * RHO0 : 0.0);
+        stc(raw + k, (R)v);
+    }
+}
+
+// Rest state f_i = w_i rho0 as raw storage in lat[(t+1)&1].
+template <typename T>
+__global__ void k_fill_rest(KArgs a) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    const int64_t t = a.ctrl->t;
+    T *raw = (T *)(((t + 1) & 1) ? a.lat1 : a.lat0);
+    const int64_t total = (int64_t)Q * a.N;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / a.N);
+        stc(raw + k, OFF ? R(0) : (R)(wgt<double>(i) * RHO0));
+    }
+}
+
+// obs component (internal order) -> caller order, in device memory.
+__global__ void k_gather_obs(const double *__restrict__ src, const int64_t *__restrict__ c2g, int64_t n,
+                             double *__restrict__ out) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = src[c2g[k]];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+static int step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStream_t st, int part) {
+    KArgs a = a0;
+    if (n_bulk > 0 && part != 2) {
+        a.e_off = 0;
+        hipLaunchKernelGGL((k_step<T, M_BULK>), dim3(n_bulk), dim3(block), 0, st, a);
+    }
+    if (n_bnd > 0 && part != 1) {
+        a.e_off = n_bulk;
+        hipLaunchKernelGGL((k_step<T, M_BND>), dim3(n_bnd), dim3(block), 0, st, a);
+    }
+    if (part != 1) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, 0);
+    return (int)hipGetLastError();
+}
+
+template <typename T>
+static int init_t(const KArgs &a0, int n_entries, int block, hipStream_t st) {
+    KArgs a = a0;
+    a.e_off = 0;
+    a.xcd_remap = 0;
+    hipLaunchKernelGGL((k_step<T, M_RAW>), dim3(n_entries), dim3(block), 0, st, a);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, 1);
+    return (int)hipGetLastError();
+}
+
+static int grid_for(int64_t total) {
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+int launch_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part) {
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == PREC_F64) return step_t<double>(a, n_bulk, n_bnd, block, st, part);
+    if (prec == PREC_F32) return step_t<float>(a, n_bulk, n_bnd, block, st, part);
+    return step_t<__half>(a, n_bulk, n_bnd, block, st, part);
+}
+
+int launch_init(int prec, const KArgs &a, int n_entries, int block, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == PREC_F64) return init_t<double>(a, n_entries, block, st);
+    if (prec == PREC_F32) return init_t<float>(a, n_entries, block, st);
+    return init_t<__half>(a, n_entries, block, st);
+}
+
+int launch_observe(int prec, const KArgs &a, int n_entries, int block, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == PREC_F64)
+        hipLaunchKernelGGL(k_observe<double>, dim3(n_entries), dim3(block), 0, st, a);
+    else if (prec == PREC_F32)
+        hipLaunchKernelGGL(k_observe<float>, dim3(n_entries), dim3(block), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_observe<__half>, dim3(n_entries), dim3(block), 0, st, a);
+    return (int)hipGetLastError();
+}
+
+int launch_load_raw(int prec, const KArgs &a, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int g = grid_for((int64_t)Q * a.N);
+    if (prec == PREC_F64)
+        hipLaunchKernelGGL(k_load_raw<double>, dim3(g), dim3(256), 0, st, a);
+    else if (prec == PREC_F32)
+        hipLaunchKernelGGL(k_load_raw<float>, dim3(g), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_load_raw<__half>, dim3(g), dim3(256), 0, st, a);
+    return (int)hipGetLastError();
+}
+
+int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *out, void *stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_gather_obs, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, src, c2g, n, out);
+    return (int)hipGetLastError();
+}
+
+int launch_fill_rest(int prec, const KArgs &a, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int g = grid_for((int64_t)Q * a.N);
+    if (prec == PREC_F64)
+        hipLaunchKernelGGL(k_fill_rest<double>, dim3(g), dim3(256), 0, st, a);
+    else if (prec == PREC_F32)
+        hipLaunchKernelGGL(k_fill_rest<float>, dim3(g), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_fill_rest<__half>, dim3(g), dim3(256), 0, st, a);
+    return (int)hipGetLastError();
+}
+
+}  // namespace hl

@@ -1,0 +1,103 @@
+"""CPU-side checks of the C ABI library: it loads, exports every entry point
+the public header declares, and its host-only validation returns the
+documented codes.  No device work runs here."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hemelb_hip.h")
+
+
+@pytest.fixture(scope="module")
+def hl():
+    import paper_2010_04144_amd as hl
+    hl.lib()
+    return hl
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hl_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(hl):
+    names = declared_functions()
+    assert len(names) >= 35
+    lib = ct.CDLL(hl._lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(hl._lib.SIGNATURES), set(names) ^ set(hl._lib.SIGNATURES)
+
+
+def test_status_strings(hl):
+    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2):
+        s = hl.status_string(code)
+        assert s and s != "unknown status"
+    assert hl.status_string(12345) == "unknown status"
+
+
+def test_validate_accepts_generated_geometries(hl):
+    for g in (synth.cylinder(), synth.tubes(3), synth.cylinder(nz=4, ends="periodic"),
+              synth.tree_geometry(3, 6.0, 1, lam=6.0)):
+        assert hl.hl_validate_sites(g.nbr, len(g.iolets)) == hl.HL_OK
+
+
+def test_validate_rejects_malformed_lists(hl):
+    g = synth.cylinder(nz=6)
+    n = g.n
+    nbr = g.nbr.copy()
+    nbr[0, 3] = 4                              # rest entry must be the site itself
+    assert hl.hl_validate_sites(nbr, 2) == hl.HL_E_RANGE
+    nbr = g.nbr.copy()
+    nbr[1, 10] = n + 5                          # index beyond the list
+    assert hl.hl_validate_sites(nbr, 2) == hl.HL_E_RANGE
+    nbr = g.nbr.copy()
+    nbr[1, 10] = -2 - 7                         # unknown iolet code
+    assert hl.hl_validate_sites(nbr, 2) == hl.HL_E_RANGE
+    nbr = g.nbr.copy()
+    s = int(np.flatnonzero(nbr[1] >= 0)[0])
+    nbr[1, s] = int(np.flatnonzero(nbr[1] >= 0)[5])   # link whose reverse does not come back
+    assert hl.hl_validate_sites(nbr, 2) == hl.HL_E_INVAL
+    nbr = g.nbr.copy()
+    inl = int(np.flatnonzero((nbr == -2).any(0))[0])
+    k = int(np.flatnonzero(nbr[:, inl] == -1)[0]) if (nbr[:, inl] == -1).any() else 1
+    nbr[k, inl] = -3                            # same site borders inlet and outlet
+    assert hl.hl_validate_sites(nbr, 2) == hl.HL_E_INVAL
+
+
+def test_validate_edge_sizes(hl):
+    empty = np.zeros((19, 0), np.int32)
+    assert hl.hl_validate_sites(empty, 0) == hl.HL_OK
+    one = np.full((19, 1), -1, np.int32)
+    one[0, 0] = 0
+    assert hl.hl_validate_sites(one, 0) == hl.HL_OK
+    lib = hl.lib()
+    assert lib.hl_validate_sites(-1, None, 0) == hl.HL_E_RANGE
+    assert lib.hl_validate_sites(2**31, None, 0) == hl.HL_E_RANGE
+
+
+def test_create_without_a_device_fails_cleanly(hl):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ct.c_void_p()
+    assert hl.lib().hl_create(ct.byref(h), 0, hl.HL_F64, 0) == hl.HL_E_DEVICE
+    assert not h.value
+    with pytest.raises(hl.HLError):
+        hl.Context(0, "f64")
+
+
+def test_bad_arguments_rejected_before_device(hl):
+    lib = hl.lib()
+    h = ct.c_void_p()
+    assert lib.hl_create(ct.byref(h), 0, 7, 0) == hl.HL_E_INVAL
+    assert lib.hl_create(ct.byref(h), 0, 0, 3) == hl.HL_E_INVAL
+    assert lib.hl_create(None, 0, 0, 0) == hl.HL_E_INVAL
+    lib.hl_destroy(None)

@@ -1,0 +1,289 @@
+"""GPU parity of the HIP library against the FP64 CPU oracle, through the C
+ABI.  FP64 storage must agree to 1e-12 (relative, metrics in scenarios.py);
+the FP32 and FP16 offset storage forms report their errors against the same
+oracle and must stay inside the bounds written in each test."""
+import numpy as np
+import pytest
+
+import synth
+from scenarios import Dom, Scenario, build_gpu, build_oracle, errors
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def hl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_04144_amd as hl
+    hl.lib()
+    return hl
+
+
+def run_both(sc, hl, oracle_mod, steps, precision="f64", gpu_steps_chunks=None):
+    o = build_oracle(sc, oracle_mod)
+    g = build_gpu(sc, hl, precision)
+    o.step(steps)
+    for n in (gpu_steps_chunks or [steps]):
+        g.step(n)
+    g.sync()
+    return g, o
+
+
+def c1_scenario(q="half", bouzidi=False, nz=64):
+    geo = synth.cylinder(nz=nz, q=q, seed=3)
+    return Scenario([Dom(geo, tau=0.8, bouzidi=bouzidi, inlets={0: (0.01, (), (), 1.0)},
+                         outlets={1: (1.0, (), (), 1.0)})])
+
+
+def check64(err, tol=TOL64):
+    bad = {k: v for k, v in err.items() if not v <= tol}
+    assert not bad, (bad, err)
+
+
+def test_c1_cylinder_fp64_1000_steps(hl, oracle_mod):
+    """The plain method on the straight cylinder: SBB walls, parabolic
+    velocity inlet, pressure outlet, tau 0.8, 1000 steps."""
+    g, o = run_both(c1_scenario(), hl, oracle_mod, 1000)
+    err = errors(g, o)
+    print("C1 fp64", err, flush=True)
+    check64(err)
+    assert g.t == 1000 == o.t
+
+
+def test_c1_bouzidi_fp64(hl, oracle_mod):
+    g, o = run_both(c1_scenario(q="cylinder", bouzidi=True), hl, oracle_mod, 400)
+    check64(errors(g, o))
+
+
+def test_tree_bouzidi_random_q_fp64(hl, oracle_mod):
+    """Small Murray tree (depth 3) with wall fractions uniform in (0, 1] per
+    link, tau 0.55, steady inlet: the configuration of the branching-artery
+    workload at a size the oracle runs in seconds."""
+    geo = synth.tree_geometry(3, 7.0, 20100416, lam=6.0)
+    outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}
+    sc = Scenario([Dom(geo, tau=0.55, bouzidi=True, inlets={0: (0.01, (), (), 1.0)}, outlets=outs)])
+    g, o = run_both(sc, hl, oracle_mod, 300)
+    err = errors(g, o)
+    print("tree fp64", geo.n, err, flush=True)
+    check64(err)
+
+
+def test_pulsatile_inlet_outlet_series_and_force(hl, oracle_mod):
+    geo = synth.tubes(2, radius=4.0, length=20)
+    sc = Scenario([Dom(geo, tau=0.7, F0=(0.0, 1e-6, 2e-6), omega=0.05,
+                       inlets={0: (0.008, (0.002, -0.001, 0.0005), (0.001, 0.0, -0.0007), 60.0),
+                               1: (0.004, (0.001,), (0.0,), 45.0)},
+                       outlets={2: (1.0, (0.0005,), (0.0002,), 80.0), 3: (1.001, (), (), 1.0)})])
+    g, o = run_both(sc, hl, oracle_mod, 250)
+    check64(errors(g, o))
+    np.testing.assert_allclose(g.iolet_bc(0, which=1), o.last_bc(0), rtol=1e-13, atol=1e-15)
+
+
+def test_periodic_womersley_pipe_fp64(hl, oracle_mod):
+    geo = synth.cylinder(nz=4, ends="periodic")
+    sc = Scenario([Dom(geo, tau=0.8, F0=(0.0, 0.0, 1e-5), omega=0.025)])
+    g, o = run_both(sc, hl, oracle_mod, 300)
+    check64(errors(g, o))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_coupled_1to3_fp64(hl, oracle_mod, mode):
+    """Arterial tube coupled 1:3 to three venous tubes, alternating and
+    both-each-step coupling, 600 steps."""
+    art = synth.tubes(1, radius=4.0, length=24)
+    ven = synth.tubes(3, radius=4.0, length=24)
+    dp = [0.30, 0.52, 0.69]
+    s = oracle_mod.velocity_factors(dp, [1.0, 0.6156, 0.5639], [1, 1, 1], 1.0)
+    sc = Scenario([Dom(art, tau=0.8, inlets={0: (0.01, (), (), 1.0)}),
+                   Dom(ven, tau=0.8)],
+                  pairs=[(0, 1, 1, i, float(s[i]), dp[i]) for i in range(3)], mode=mode)
+    g, o = run_both(sc, hl, oracle_mod, 600)
+    for d in (0, 1):
+        err = errors(g, o, d)
+        print("coupled", mode, d, err, flush=True)
+        check64(err)
+    for d in (0, 1):
+        np.testing.assert_allclose(g.iolet_bc(d, which=1), o.last_bc(d), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("prec,bound_u,bound_rho", [("f32", 2e-4, 2e-4), ("f16", 0.05, 0.05)])
+def test_offset_storage_errors(hl, oracle_mod, prec, bound_u, bound_rho):
+    """FP32 / FP16 storage of f - w rho0 with FP32 arithmetic on the cylinder
+    after 1000 steps: the errors against the FP64 oracle are reported and
+    bounded."""
+    g, o = run_both(c1_scenario(), hl, oracle_mod, 1000, precision=prec)
+    err = errors(g, o, with_f=True, with_wss=True)
+    print(prec, "C1 errors vs oracle", err, flush=True)
+    assert err["e_u"] < bound_u and err["e_rho"] < bound_rho
+
+
+def test_rest_state_stays_exact(hl):
+    """Rest state with closed ends: FP64 stays at w_i; offset forms stay 0."""
+    for prec in ("f64", "f32", "f16"):
+        geo = synth.cylinder(nz=8, q="random", seed=4)
+        sc = Scenario([Dom(geo, bouzidi=True, inlets={0: (0.0, (), (), 1.0)}, outlets={1: (1.0, (), (), 1.0)})])
+        g = build_gpu(sc, hl, prec)
+        g.step(20)
+        f = g.populations(0)
+        from scenarios import W
+        assert np.abs(f - W[:, None]).max() < (1e-16 if prec != "f64" else 5e-16)
+
+
+def test_graph_and_launch_drivers_are_bitwise_equal(hl):
+    res = []
+    for drive, spg in ((hl.HL_DRIVE_LAUNCH, 1), (hl.HL_DRIVE_GRAPH, 7)):
+        g = build_gpu(c1_scenario(nz=16), hl)
+        g.set_drive(drive, spg)
+        g.step(45)
+        res.append(g.populations(0))
+    assert np.array_equal(res[0], res[1])
+
+
+def test_checkpoint_resume_bitwise(hl):
+    for prec in ("f64", "f32", "f16"):
+        a = build_gpu(c1_scenario(nz=16), hl, prec)
+        a.step(60)
+        ref = a.populations(0)
+        b = build_gpu(c1_scenario(nz=16), hl, prec)
+        b.step(30)
+        blob = b.get_state()
+        c = build_gpu(c1_scenario(nz=16), hl, prec)
+        c.commit()
+        c.set_state(blob)
+        assert c.t == 30
+        c.step(30)
+        assert np.array_equal(c.populations(0), ref), prec
+
+
+def test_set_populations_round_trip_is_bitwise(hl):
+    a = build_gpu(c1_scenario(nz=16), hl)
+    a.step(50)
+    ref = a.populations(0)
+    b = build_gpu(c1_scenario(nz=16), hl)
+    b.step(20)
+    f20 = b.populations(0)
+    b.set_populations(0, f20)
+    assert np.array_equal(b.populations(0), f20)
+    b.step(30)
+    assert np.array_equal(b.populations(0), ref)
+
+
+def test_set_populations_matches_oracle(hl, oracle_mod):
+    """Load a perturbed state into both and step on."""
+    sc = c1_scenario(nz=16)
+    o = build_oracle(sc, oracle_mod)
+    g = build_gpu(sc, hl)
+    rng = np.random.default_rng(9)
+    from scenarios import W
+    f = W[:, None] * (1.0 + 0.01 * rng.standard_normal((19, o.n[0])))
+    o.set_f(0, f)
+    g.set_populations(0, f)
+    o.step(80)
+    g.step(80)
+    check64(errors(g, o))
+
+
+def test_nan_is_reported_as_divergence(hl):
+    g = build_gpu(c1_scenario(nz=8), hl)
+    g.step(3)
+    f = g.populations(0)
+    f[4, 17] = np.nan
+    g.set_populations(0, f)
+    with pytest.raises(hl.HLError) as ei:
+        g.step(2)
+        g.sync()
+    assert ei.value.code == hl.HL_E_DIVERGED
+
+
+@pytest.mark.parametrize("block,flags", [(64, 0), (128, 1), (256, 1)])
+def test_schedules_agree(hl, oracle_mod, block, flags):
+    sc = c1_scenario(nz=24)
+    o = build_oracle(sc, oracle_mod)
+    g = build_gpu(sc, hl)
+    g.set_schedule(block, flags)
+    o.step(200)
+    g.step(200)
+    check64(errors(g, o))
+
+
+def test_empty_domain_and_ragged_sizes(hl, oracle_mod):
+    """A domain without sites next to one whose site count is not a multiple
+    of any work-group size."""
+    geo = synth.cylinder(nx=9, ny=9, nz=7, radius=3.3, ends="periodic")
+    assert geo.n % 64 != 0
+    sc = Scenario([Dom(geo, tau=0.9, F0=(0, 0, 1e-5))])
+    o = build_oracle(sc, oracle_mod)
+    g = hl.Context(0, "f64")
+    e = g.add_domain()
+    g.load_sites(e, np.zeros((3, 0), np.int32), np.zeros((19, 0), np.int32), 0)
+    d = g.add_domain()
+    g.load_geometry(d, geo)
+    g.set_tau(d, 0.9)
+    g.set_body_force(d, (0, 0, 1e-5))
+    o.step(100)
+    g.step(100)
+    check64(errors(g, o, dom=d, dom_o=0))
+    assert g.density(e).shape == (0,)
+
+
+def test_nothing_loaded_is_a_state_error(hl):
+    g = hl.Context(0, "f64")
+    g.add_domain()
+    with pytest.raises(hl.HLError) as ei:
+        g.step(1)
+    assert ei.value.code == hl.HL_E_STATE
+
+
+def test_argument_errors(hl):
+    g = build_gpu(c1_scenario(nz=8), hl)
+    with pytest.raises(hl.HLError) as ei:
+        g.set_tau(0, 0.5)
+    assert ei.value.code == hl.HL_E_INVAL
+    assert g.set_tau(0, 1.2) == hl.HL_W_TAU
+    assert g.set_inlet_velocity(0, 0, 0.07) == hl.HL_W_MACH
+    g.set_inlet_velocity(0, 0, 0.01)
+    with pytest.raises(hl.HLError) as ei:
+        g.set_inlet_velocity(0, 1, 0.01)          # iolet 1 is an outlet
+    assert ei.value.code == hl.HL_E_INVAL
+    with pytest.raises(hl.HLError) as ei:
+        g.set_tau(5, 0.8)
+    assert ei.value.code == hl.HL_E_RANGE
+    g.step(1)
+    with pytest.raises(hl.HLError) as ei:
+        g.add_domain()
+    assert ei.value.code == hl.HL_E_STATE
+    with pytest.raises(hl.HLError):
+        g.set_schedule(100, 0)
+
+
+def test_device_reads_match_host_reads(hl):
+    import torch
+    g = build_gpu(c1_scenario(nz=16), hl)
+    g.step(40)
+    n = g.n[0]
+    rho = torch.empty(n, dtype=torch.float64, device="cuda")
+    u = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    g.set_stream(torch.cuda.current_stream())
+    g.density_device(0, rho)
+    g.velocity_device(0, u)
+    g.wss_device(0, w)
+    torch.cuda.synchronize()
+    assert np.array_equal(rho.cpu().numpy(), g.density(0))
+    assert np.array_equal(u.cpu().numpy(), g.velocity(0))
+    assert np.array_equal(w.cpu().numpy(), g.wss(0))
+
+
+def test_autotune_keeps_state(hl):
+    a = build_gpu(c1_scenario(nz=24), hl)
+    a.step(10)
+    before = a.populations(0)
+    a.autotune(50)
+    assert a.t == 10
+    assert np.array_equal(a.populations(0), before)
+    blk, flags = a.schedule()
+    assert blk in (64, 128, 256)
