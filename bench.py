@@ -54,8 +54,8 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def make_ctx(hl, geo, prec, torch):
-    ctx = hl.Context(0, prec)
+def make_ctx(hl, geo, prec, torch, order=0):
+    ctx = hl.Context(0, prec, order=order)
     d = ctx.add_domain()
     ctx.load_geometry(d, geo)
     ctx.set_tau(d, TAU)
@@ -66,8 +66,8 @@ def make_ctx(hl, geo, prec, torch):
     return ctx
 
 
-def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms):
-    ctx = make_ctx(hl, geo, prec, torch)
+def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms, order):
+    ctx = make_ctx(hl, geo, prec, torch, order)
     if autotune_ms > 0:
         ctx.autotune(autotune_ms)
     ctx.step(warmup)
@@ -200,7 +200,8 @@ def main():
     ap.add_argument("--box", type=int, default=768)
     ap.add_argument("--precisions", default="f64,f32,f16")
     ap.add_argument("--kernel-steps", type=int, default=50)
-    ap.add_argument("--autotune-ms", type=int, default=0)
+    ap.add_argument("--autotune-ms", type=int, default=300)
+    ap.add_argument("--order", type=int, default=2, help="hl_create layout flags (HL_ORDER_*)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and full-size parity")
@@ -230,7 +231,8 @@ def main():
     runs, fields = {}, {}
     for p in precs:
         runs[p], fields[p] = None, None
-        res, u, rho = run_precision(hl, torch, geo, p, args.steps, args.warmup, args.kernel_steps, args.autotune_ms)
+        res, u, rho = run_precision(hl, torch, geo, p, args.steps, args.warmup, args.kernel_steps, args.autotune_ms,
+                                    args.order)
         runs[p] = res
         fields[p] = (u, rho)
     if "f64" in fields:
@@ -275,6 +277,7 @@ def main():
             "storage": {"f64": "FP64", "f32": "FP32 offset f - w rho0", "f16": "FP16 offset f - w rho0"}[head],
             "arithmetic": "FP64" if head == "f64" else "FP32",
             "scheme": "two-lattice pull, int32 pull table",
+            "layout_flags": args.order,
         },
         "roofline": {
             "bound": "hbm",

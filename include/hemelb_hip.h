@@ -73,6 +73,17 @@ extern "C" {
 #define HL_DRIVE_LAUNCH 0 /* plain kernel launches per step */
 #define HL_DRIVE_GRAPH 1  /* replay of a captured HIP graph of several steps (default) */
 
+/* hl_create flags: internal site order inside each class of sites (bulk
+ * sites; boundary sites of one domain or one iolet).  The caller order is
+ * kept by default; Morton order (bit-interleaved x, y, z) keeps spatial
+ * neighbours close in memory. */
+#define HL_ORDER_BULK_MORTON 1u
+#define HL_ORDER_BOUNDARY_MORTON 2u
+/* keep wall sites in place among the bulk sites (only iolet sites are
+ * grouped); a work-group whose sites all lack boundary links takes the bulk
+ * kernel, any other one the boundary kernel */
+#define HL_ORDER_INTERLEAVE 4u
+
 /* schedule flags */
 #define HL_SCHED_XCD_REMAP 1u /* hand each XCD a contiguous range of site blocks */
 
@@ -99,9 +110,9 @@ typedef struct {
 /* ---- context ----------------------------------------------------------- */
 
 /* Create a context on HIP device `device` storing populations in `precision`
- * (HL_F64, HL_F32_OFFSET, HL_F16_OFFSET).  `flags` is reserved (0).
- * Errors: HL_E_INVAL (bad precision or flags), HL_E_DEVICE (no such device,
- * or not gfx950).  *out is NULL on error. */
+ * (HL_F64, HL_F32_OFFSET, HL_F16_OFFSET); `flags` is 0 or a combination of
+ * HL_ORDER_* bits.  Errors: HL_E_INVAL (bad precision or flags), HL_E_DEVICE
+ * (no such device, or not gfx950).  *out is NULL on error. */
 int hl_create(hl_ctx **out, int device, int precision, uint64_t flags);
 
 /* Release the context and its device memory.  NULL is allowed; calling it

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (HL_ALTERNATE, HL_BOTH_EACH_STEP, HL_DRIVE_GRAPH, HL_DRIVE_LAUNCH,  # noqa: F401
                    HL_E_DEVICE, HL_E_DIVERGED, HL_E_INVAL, HL_E_NOMEM, HL_E_RANGE, HL_E_STATE,
                    HL_F16_OFFSET, HL_F32_OFFSET, HL_F64, HL_INLET_VEL, HL_OK, HL_OUTLET_P,
-                   HL_SCHED_XCD_REMAP, HL_W_MACH, HL_W_TAU, HL_WALL_BOUZIDI, HL_WALL_SBB, hl_info)
+                   HL_ORDER_BOUNDARY_MORTON, HL_ORDER_BULK_MORTON, HL_ORDER_INTERLEAVE, HL_SCHED_XCD_REMAP, HL_W_MACH, HL_W_TAU, HL_WALL_BOUZIDI, HL_WALL_SBB, hl_info)
 
 PRECISIONS = {"f64": HL_F64, "f32": HL_F32_OFFSET, "f16": HL_F16_OFFSET}
 
@@ -49,11 +49,11 @@ def _pd(a):
 class Context:
     """One library context: several domains stepped together on one GPU."""
 
-    def __init__(self, device=0, precision="f64"):
+    def __init__(self, device=0, precision="f64", order=0):
         self._l = lib()
         self._h = ct.c_void_p()
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        rc = self._l.hl_create(ct.byref(self._h), int(device), prec, 0)
+        rc = self._l.hl_create(ct.byref(self._h), int(device), prec, int(order))
         if rc != HL_OK:
             raise HLError(rc, f"hl_create failed: {status_string(rc)}")
         self.precision = prec

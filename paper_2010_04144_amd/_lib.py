@@ -34,6 +34,9 @@ HL_BOTH_EACH_STEP = 1
 HL_DRIVE_LAUNCH = 0
 HL_DRIVE_GRAPH = 1
 HL_SCHED_XCD_REMAP = 1
+HL_ORDER_BULK_MORTON = 1
+HL_ORDER_BOUNDARY_MORTON = 2
+HL_ORDER_INTERLEAVE = 4
 
 
 class hl_info(ct.Structure):

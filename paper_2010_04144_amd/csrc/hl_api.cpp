@@ -25,6 +25,17 @@ constexpr int CYh[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1
 constexpr int CZh[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 inline int opp_h(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
+// Spread the low 21 bits of v to every third bit.
+inline uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
 struct Series {
     double a0 = 0.0;
     int nh = 0;
@@ -86,6 +97,7 @@ struct Range {
 
 struct hl_ctx {
     int device = 0, precision = 0;
+    uint64_t order_flags = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     std::string err;
@@ -101,7 +113,7 @@ struct hl_ctx {
     // layout
     int64_t N = 0, NB = 0, IO0 = 0, Nb = 0, Nio = 0;
     std::vector<Range> ranges;
-    int n_bulk_ranges = 0;
+    std::vector<uint8_t> site_wall;  // interleaved layout: 1 where a site has a boundary link
     std::vector<hl::Entry> entries;
     int n_bulk_blocks = 0, n_bnd_blocks = 0;
     std::vector<hl::SegDev> hseg;
@@ -245,32 +257,45 @@ hl::KArgs make_args(hl_ctx *c) {
     return a;
 }
 
-// Split the class ranges into work-group entries of at most `block` sites.
+// Split the class ranges into work-group entries of at most `block` sites:
+// entries for the bulk kernel first, then those for the boundary kernel.  In
+// the interleaved layout a chunk of a mixed range goes to the bulk kernel
+// when none of its sites has a boundary link.
+constexpr int32_t K_MIXED = 3;
+
 void build_entries(hl_ctx *c) {
-    c->entries.clear();
+    std::vector<hl::Entry> bulk, bnd;
     for (auto &io : c->hio) io.e_lo = io.e_hi = 0;
-    int nb = 0;
-    for (size_t r = 0; r < c->ranges.size(); ++r) {
-        const Range &g = c->ranges[r];
+    for (const Range &g : c->ranges) {
         const int klass = g.tag & 3;
-        const int first = (int)c->entries.size();
         for (int64_t off = 0; off < g.count; off += c->block) {
             hl::Entry e;
             e.start = (int32_t)(g.start + off);
             e.count = (int32_t)std::min<int64_t>(c->block, g.count - off);
             e.seg = g.seg;
             e.tag = g.tag;
-            c->entries.push_back(e);
+            if (klass == K_MIXED) {
+                bool wall = false;
+                for (int32_t k = 0; k < e.count && !wall; ++k) wall = c->site_wall[(size_t)e.start + k] != 0;
+                e.tag = wall ? hl::K_WALL : hl::K_BULK;
+            }
+            if ((e.tag & 3) == hl::K_BULK)
+                bulk.push_back(e);
+            else
+                bnd.push_back(e);
         }
-        if (klass == hl::K_IOLET) {
-            auto &io = c->hio[g.tag >> 2];
-            io.e_lo = first;
-            io.e_hi = (int)c->entries.size();
-        }
-        if ((int)r < c->n_bulk_ranges) nb = (int)c->entries.size();
     }
-    c->n_bulk_blocks = nb;
-    c->n_bnd_blocks = (int)c->entries.size() - nb;
+    c->entries = bulk;
+    c->entries.insert(c->entries.end(), bnd.begin(), bnd.end());
+    c->n_bulk_blocks = (int)bulk.size();
+    c->n_bnd_blocks = (int)bnd.size();
+    for (int e = 0; e < (int)c->entries.size(); ++e) {
+        const hl::Entry &en = c->entries[e];
+        if ((en.tag & 3) != hl::K_IOLET) continue;
+        auto &io = c->hio[en.tag >> 2];
+        if (io.e_hi == 0) io.e_lo = e;
+        io.e_hi = e + 1;
+    }
 }
 
 int upload_schedule(hl_ctx *c) {
@@ -431,25 +456,69 @@ int commit(hl_ctx *c) {
             cls[d][x] = k >= 0 ? k : (wall ? -2 : -1);
         }
     }
-    // internal order
+    // internal order: bulk, wall, iolet groups; inside a group caller order or
+    // Morton order of the coordinates
     c->ranges.clear();
     int64_t pos = 0;
-    for (int d = 0; d < D; ++d) {
+    auto place = [&](int d, int32_t key, bool morton) {
         Domain &dm = c->doms[d];
-        dm.c2g.assign(dm.n, -1);
-        const int64_t st = pos;
+        std::vector<int64_t> idx;
         for (int64_t x = 0; x < dm.n; ++x)
-            if (cls[d][x] == -1) dm.c2g[x] = pos++;
-        if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_BULK});
-    }
-    c->n_bulk_ranges = (int)c->ranges.size();
-    c->NB = pos;
-    for (int d = 0; d < D; ++d) {
-        Domain &dm = c->doms[d];
-        const int64_t st = pos;
-        for (int64_t x = 0; x < dm.n; ++x)
-            if (cls[d][x] == -2) dm.c2g[x] = pos++;
-        if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_WALL});
+            if (cls[d][x] == key) idx.push_back(x);
+        if (morton) {
+            std::vector<std::pair<uint64_t, int64_t>> kv(idx.size());
+            for (size_t m = 0; m < idx.size(); ++m) {
+                const int64_t x = idx[m];
+                const uint64_t mx = (uint64_t)(dm.coords[x] + (1 << 20));
+                const uint64_t my = (uint64_t)(dm.coords[(size_t)dm.n + x] + (1 << 20));
+                const uint64_t mz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] + (1 << 20));
+                kv[m] = {spread3(mx) | (spread3(my) << 1) | (spread3(mz) << 2), x};
+            }
+            std::sort(kv.begin(), kv.end());
+            for (size_t m = 0; m < idx.size(); ++m) idx[m] = kv[m].second;
+        }
+        for (int64_t x : idx) dm.c2g[x] = pos++;
+        return (int64_t)idx.size();
+    };
+    const bool mb = (c->order_flags & HL_ORDER_BULK_MORTON) != 0;
+    const bool mw = (c->order_flags & HL_ORDER_BOUNDARY_MORTON) != 0;
+    const bool inter = (c->order_flags & HL_ORDER_INTERLEAVE) != 0;
+    if (inter) {
+        // bulk and wall sites together, in one range per domain
+        for (int d = 0; d < D; ++d) {
+            for (auto &v : cls[d])
+                if (v == -2) v = -3;  // wall, placed with the bulk sites below
+            c->doms[d].c2g.assign(c->doms[d].n, -1);
+        }
+        for (int d = 0; d < D; ++d) {
+            auto &cd = cls[d];
+            std::vector<int32_t> saved = cd;
+            for (auto &v : cd)
+                if (v == -3) v = -1;
+            const int64_t st = pos;
+            place(d, -1, mb);
+            cd = saved;
+            if (pos > st) c->ranges.push_back({st, pos - st, d, K_MIXED});
+        }
+        c->NB = 0;
+        c->site_wall.assign(pos, 0);
+        for (int d = 0; d < D; ++d)
+            for (int64_t x = 0; x < c->doms[d].n; ++x)
+                if (cls[d][x] == -3) c->site_wall[c->doms[d].c2g[x]] = 1;
+        for (int d = 0; d < D; ++d)
+            for (auto &v : cls[d])
+                if (v == -3) v = -2;
+    } else {
+        for (int d = 0; d < D; ++d) {
+            c->doms[d].c2g.assign(c->doms[d].n, -1);
+            const int64_t st = pos;
+            if (place(d, -1, mb) > 0) c->ranges.push_back({st, pos - st, d, hl::K_BULK});
+        }
+        c->NB = pos;
+        for (int d = 0; d < D; ++d) {
+            const int64_t st = pos;
+            if (place(d, -2, mw) > 0) c->ranges.push_back({st, pos - st, d, hl::K_WALL});
+        }
     }
     c->IO0 = pos;
     std::vector<int64_t> io_lo(io_count, 0), io_n(io_count, 0);
@@ -457,8 +526,7 @@ int commit(hl_ctx *c) {
         Domain &dm = c->doms[d];
         for (int k = 0; k < dm.n_iolet; ++k) {
             const int64_t st = pos;
-            for (int64_t x = 0; x < dm.n; ++x)
-                if (cls[d][x] == k) dm.c2g[x] = pos++;
+            place(d, k, mw);
             io_lo[dm.io_base + k] = st;
             io_n[dm.io_base + k] = pos - st;
             if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_IOLET | ((dm.io_base + k) << 2)});
@@ -730,7 +798,8 @@ const char *hl_last_error(const hl_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     if (!out) return HL_E_INVAL;
     *out = nullptr;
-    if (precision < HL_F64 || precision > HL_F16_OFFSET || flags != 0) return HL_E_INVAL;
+    if (precision < HL_F64 || precision > HL_F16_OFFSET) return HL_E_INVAL;
+    if (flags & ~(uint64_t)(HL_ORDER_BULK_MORTON | HL_ORDER_BOUNDARY_MORTON | HL_ORDER_INTERLEAVE)) return HL_E_INVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HL_E_DEVICE;
     hipDeviceProp_t prop;
@@ -740,6 +809,7 @@ int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     hl_ctx *c = new hl_ctx();
     c->device = device;
     c->precision = precision;
+    c->order_flags = flags;
     if (hipHostMalloc((void **)&c->h_nan, sizeof(int), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return HL_E_NOMEM;

@@ -116,30 +116,44 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
             uz = up[2 * a.Nio + vi];
         }
     }
+    // Phase 1: issue every load the boundary rules need before using any of
+    // them, so the memory latencies overlap instead of queueing behind the
+    // per-direction branches.
+    const bool bz = sg.wall_mode == WALL_BOUZIDI;
+    const bool outlet = klass == K_IOLET && kind == KIND_OUTLET;
+    R own[Q];  // f*_i(s) where a rule reads it
+    R qv[Q];   // wall fraction of the wall link fed into direction j
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int ib = opp(i);
+        // f*_i(s) feeds direction ib (bounce-back, Bouzidi, inlet) and, for a
+        // Bouzidi wall link, direction i itself (q >= 1/2)
+        const bool need = (sr[ib] == -1) || (sr[ib] <= -2 && !outlet) || (bz && sr[i] == -1);
+        own[i] = need ? ldc(lin + (size_t)i * N + s) : R(0);
+        qv[i] = (bz && sr[i] == -1) ? (R)a.bq[(size_t)(i - 1) * a.Nb + b] : R(0.5);
+    }
+    // Phase 2: the boundary rules, from registers only.
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
         if (sr[j] >= 0) continue;
         const int jb = opp(j);
         if (sr[j] == -1) {
             // wall link (s, jb): the wall lies at x_s + q c_jb
-            const R own_opp = ldc(lin + (size_t)jb * N + s);  // f*_jb(s)
-            if (sg.wall_mode == WALL_BOUZIDI) {
-                const R q = (R)a.bq[(size_t)(j - 1) * a.Nb + b];
+            if (bz) {
+                const R q = qv[j];
                 if (q < R(0.5)) {
                     // second node x_s - c_jb = x_s + c_j, pulled as x[jb]
-                    x[j] = (sr[jb] >= 0) ? R(2) * q * own_opp + (R(1) - R(2) * q) * x[jb] : own_opp;
+                    x[j] = (sr[jb] >= 0) ? R(2) * q * own[jb] + (R(1) - R(2) * q) * x[jb] : own[jb];
                 } else {
-                    const R own = ldc(lin + (size_t)j * N + s);  // f*_j(s)
-                    x[j] = own_opp / (R(2) * q) + (R(1) - R(1) / (R(2) * q)) * own;
+                    x[j] = own[jb] / (R(2) * q) + (R(1) - R(1) / (R(2) * q)) * own[j];
                 }
             } else {
-                x[j] = own_opp;
+                x[j] = own[jb];
             }
         } else if (kind == KIND_INLET) {
             // Ladd: f_j = f*_jb - 6 w rho0 (c_jb . u_w), u_w = U phi n
-            const R own_opp = ldc(lin + (size_t)jb * N + s);
             const R cn = R(CX[jb]) * nx + R(CY[jb]) * ny + R(CZ[jb]) * nz;
-            x[j] = own_opp - R(6) * wgt<R>(j) * R(RHO0) * (cn * (U * phi));
+            x[j] = own[jb] - R(6) * wgt<R>(j) * R(RHO0) * (cn * (U * phi));
         } else {
             // pressure outlet: equilibrium at rho_out and the site's velocity
             const R cu = R(CX[j]) * ux + R(CY[j]) * uy + R(CZ[j]) * uz;

@@ -287,3 +287,22 @@ def test_autotune_keeps_state(hl):
     assert np.array_equal(a.populations(0), before)
     blk, flags = a.schedule()
     assert blk in (64, 128, 256)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 6])
+def test_site_orders_agree_with_oracle(hl, oracle_mod, order):
+    """Every internal site layout gives the oracle's result: Morton order of
+    bulk and/or boundary sites, wall sites interleaved with bulk sites."""
+    geo = synth.tree_geometry(3, 7.0, 20100416, lam=6.0)
+    outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}
+    sc = Scenario([Dom(geo, tau=0.6, bouzidi=True, inlets={0: (0.01, (), (), 1.0)}, outlets=outs)])
+    o = build_oracle(sc, oracle_mod)
+    g = hl.Context(0, "f64", order=order)
+    g.add_domain()
+    g.load_geometry(0, geo)
+    g.set_tau(0, 0.6)
+    g.set_wall_mode(0, hl.HL_WALL_BOUZIDI)
+    g.set_inlet_velocity(0, 0, 0.01)
+    o.step(150)
+    g.step(150)
+    check64(errors(g, o))
