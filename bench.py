@@ -43,10 +43,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def bytes_per_site(prec):
-    """Algorithmic HBM bytes of one bulk-site update in the two-lattice pull
-    scheme: 19 populations read and written, 18 int32 pull indices."""
-    return 2 * 19 * STORE_BYTES[prec] + 18 * 4
+def bytes_per_site(prec, aa=False):
+    """Algorithmic HBM bytes of one bulk-site update: 19 populations read and
+    written, plus 18 int32 pull indices (two-lattice pull) or, averaged over
+    an even and an odd step of the in-place scheme, 9."""
+    return 2 * 19 * STORE_BYTES[prec] + (9 if aa else 18) * 4
 
 
 def kernel_source_hash():
@@ -66,12 +67,7 @@ def make_ctx(hl, geo, prec, torch, order=0):
     return ctx
 
 
-def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms, order):
-    ctx = make_ctx(hl, geo, prec, torch, order)
-    if autotune_ms > 0:
-        ctx.autotune(autotune_ms)
-    ctx.step(warmup)
-    ctx.sync()
+def measure(ctx, torch, steps):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -82,16 +78,47 @@ def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.sync()
-    ms = e0.elapsed_time(e1)
+    return e0.elapsed_time(e1), wall
+
+
+def choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps):
+    """Layout search (site order and streaming scheme, fixed at context
+    creation) around the library's own schedule autotuner (work-group size,
+    fused or split launches, XCD order).  Returns the fastest context."""
+    best = None
+    for order in layouts:
+        ctx = make_ctx(hl, geo, prec, torch, order)
+        if autotune_ms > 0:
+            ctx.autotune(autotune_ms)
+        ctx.step(4)
+        ms, _ = measure(ctx, torch, probe_steps)
+        log(f"{prec} layout {order}: schedule {ctx.schedule()}, {geo.n * probe_steps / (ms * 1e-3) / 1e6:.0f} MLUPS")
+        if best is None or ms < best[0]:
+            if best is not None:
+                best[2].close()
+            best = (ms, order, ctx)
+        else:
+            ctx.close()
+    return best[1], best[2]
+
+
+def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms, layouts, probe_steps):
+    order, ctx = choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps)
+    ctx.step(warmup)
+    ctx.sync()
+    t_start = ctx.t
+    ms, wall = measure(ctx, torch, steps)
     kb, kn = ctx.time_kernels(kernel_steps)
     info = ctx.info()
     u = ctx.velocity(0)
     rho = ctx.density(0)
     sched = ctx.schedule()
+    t_end = ctx.t
     ctx.close()
     n = geo.n
     mlups = n * steps / (ms * 1e-3) / 1e6
-    B = bytes_per_site(prec)
+    aa = bool(order & hl.HL_SCHEME_AA)
+    B = bytes_per_site(prec, aa)
     bulk_bytes = info["n_bulk"] * B
     res = {
         "mlups": round(mlups, 1),
@@ -101,22 +128,25 @@ def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms
         "alg_frac_peak": round(mlups * 1e6 * B / 1e9 / PEAK_HBM_GBS, 4),
         "bulk_kernel_ms": round(kb, 5),
         "boundary_kernel_ms": round(kn, 5),
-        "bulk_kernel_GBps": round(bulk_bytes / (kb * 1e-3) / 1e9, 1),
+        "bulk_kernel_GBps": round(bulk_bytes / (kb * 1e-3) / 1e9, 1) if kb > 0.01 else None,
         "bytes_per_site": B,
         "n_bulk": info["n_bulk"],
         "n_boundary": info["n_boundary"],
+        "layout_flags": order,
+        "scheme": "in-place AA" if aa else "two-lattice pull",
         "block": sched[0],
         "sched_flags": sched[1],
+        "steps_timed_from": t_start,
     }
     log(prec, json.dumps(res))
-    return res, u, rho
+    return res, u, rho, t_end, order
 
 
 def rel_err(a, b, scale):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(scale)))
 
 
-def cpu_baseline_and_parity(hl, torch, geo, seconds, threads):
+def cpu_baseline_and_parity(hl, torch, geo, seconds, threads, order=0):
     """Time the FP64 oracle on this host's cores over a bounded number of
     steps of the same workload, then run the FP64 GPU path for the same
     steps and compare."""
@@ -141,7 +171,7 @@ def cpu_baseline_and_parity(hl, torch, geo, seconds, threads):
     f_r = sysm.f(0)
     mu_r, _, _ = sysm.iolet_stats(0)
     del sysm
-    ctx = make_ctx(hl, geo, "f64", torch)
+    ctx = make_ctx(hl, geo, "f64", torch, order)
     ctx.step(steps)
     u = ctx.velocity(0)
     rho = ctx.density(0)
@@ -151,6 +181,7 @@ def cpu_baseline_and_parity(hl, torch, geo, seconds, threads):
     w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
     par = {
         "steps": steps,
+        "layout_flags": order,
         "e_u": rel_err(u, u_r, u_r),
         "e_rho": rel_err(rho, rho_r, rho_r - 1.0),
         "e_f": rel_err(f, f_r, f_r - w[:, None]),
@@ -169,7 +200,10 @@ def cpu_baseline_and_parity(hl, torch, geo, seconds, threads):
     return cpu, par
 
 
-def traffic_from_profile(prec):
+def traffic_from_profile(prec, layout, sched):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, when it was taken from the same kernel source, layout and
+    schedule; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_c2.json")
     if not os.path.exists(path):
         return None
@@ -177,7 +211,10 @@ def traffic_from_profile(prec):
         t = json.load(fh)
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return t.get(prec, {}).get("bulk_bytes_per_launch")
+    e = t.get(prec, {})
+    if e.get("layout_flags") != layout or e.get("sched_flags") != sched:
+        return None
+    return e.get("bytes_per_launch")
 
 
 def copy_calibration(torch):
@@ -200,8 +237,10 @@ def main():
     ap.add_argument("--box", type=int, default=768)
     ap.add_argument("--precisions", default="f64,f32,f16")
     ap.add_argument("--kernel-steps", type=int, default=50)
-    ap.add_argument("--autotune-ms", type=int, default=300)
-    ap.add_argument("--order", type=int, default=2, help="hl_create layout flags (HL_ORDER_*)")
+    ap.add_argument("--autotune-ms", type=int, default=400)
+    ap.add_argument("--layouts", default="2,8,24",
+                    help="hl_create layout flags to search (HL_ORDER_* | HL_SCHEME_AA)")
+    ap.add_argument("--probe-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and full-size parity")
@@ -228,32 +267,40 @@ def main():
         f"{len(geo.iolets)} iolets, {geo.q.size} wall links ({time.perf_counter() - t0:.1f} s)")
 
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
-    runs, fields = {}, {}
+    layouts = [int(v) for v in args.layouts.split(",") if v.strip()]
+    runs, fields, tends, chosen = {}, {}, {}, {}
     for p in precs:
-        runs[p], fields[p] = None, None
-        res, u, rho = run_precision(hl, torch, geo, p, args.steps, args.warmup, args.kernel_steps, args.autotune_ms,
-                                    args.order)
+        res, u, rho, t_end, order = run_precision(hl, torch, geo, p, args.steps, args.warmup, args.kernel_steps,
+                                                  args.autotune_ms, layouts, args.probe_steps)
         runs[p] = res
         fields[p] = (u, rho)
+        tends[p] = t_end
+        chosen[p] = order
     if "f64" in fields:
         u64, r64 = fields["f64"]
         for p in precs:
             if p == "f64":
                 continue
             u, r = fields[p]
+            if tends[p] != tends["f64"]:
+                continue
             runs[p]["error_vs_f64"] = {"e_u": rel_err(u, u64, u64), "e_rho": rel_err(r, r64, r64 - 1.0),
-                                       "after_steps": args.warmup + args.steps + args.kernel_steps}
+                                       "after_steps": tends[p]}
 
     cpu, parity = None, None
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-        cpu, parity = cpu_baseline_and_parity(hl, torch, geo, args.cpu_seconds, threads)
+        cpu, parity = cpu_baseline_and_parity(hl, torch, geo, args.cpu_seconds, threads, chosen.get("f64", 0))
 
     head = "f32" if "f32" in runs else precs[0]
     r = runs[head]
     B = r["bytes_per_site"]
-    achieved = r["bulk_kernel_GBps"]
-    traffic = traffic_from_profile(head)
+    fused = bool(r["sched_flags"] & hl.HL_SCHED_FUSED)
+    k_ms = r["boundary_kernel_ms"] if fused else r["bulk_kernel_ms"]
+    k_sites = geo.n if fused else r["n_bulk"]
+    achieved = round(k_sites * B / (k_ms * 1e-3) / 1e9, 1)
+    kname = ("k_aa" if r["scheme"].startswith("in-place") else "k_step") + (" fused" if fused else " bulk")
+    traffic = traffic_from_profile(head, r["layout_flags"], r["sched_flags"])
     line = {
         "metric": "MLUPS + achieved HBM GB/s (% peak), FP64 vs FP32 at stated error, 1 GPU",
         "value": r["mlups"],
@@ -276,19 +323,20 @@ def main():
             "iolets": len(geo.iolets),
             "storage": {"f64": "FP64", "f32": "FP32 offset f - w rho0", "f16": "FP16 offset f - w rho0"}[head],
             "arithmetic": "FP64" if head == "f64" else "FP32",
-            "scheme": "two-lattice pull, int32 pull table",
-            "layout_flags": args.order,
+            "scheme": r["scheme"] + ", int32 pull table",
+            "layout_flags": r["layout_flags"],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step bulk sites (" + head + ")",
+            "kernel": kname + " (" + head + ")",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
             "bytes_per_site": B,
-            "sites_per_launch": r["n_bulk"],
+            "sites_per_launch": k_sites,
+            "kernel_ms": k_ms,
         },
         "variants": runs,
         "parity": parity,

@@ -83,9 +83,21 @@ extern "C" {
  * grouped); a work-group whose sites all lack boundary links takes the bulk
  * kernel, any other one the boundary kernel */
 #define HL_ORDER_INTERLEAVE 4u
+/* brick-local layout: sites are grouped by 16^3 bricks of the voxel grid;
+ * inside a brick, bulk sites come first, then wall sites (lexicographic);
+ * iolet sites stay grouped per iolet */
+#define HL_ORDER_BRICK 8u
+/* in-place AA-pattern streaming: one population lattice instead of two
+ * (half the population memory); even steps touch only each site's own
+ * populations, odd steps gather and scatter through the pull table */
+#define HL_SCHEME_AA 16u
 
 /* schedule flags */
 #define HL_SCHED_XCD_REMAP 1u /* hand each XCD a contiguous range of site blocks */
+#define HL_SCHED_FUSED 2u     /* one launch over all work-groups in storage order, each taking the
+                                 bulk or the boundary path */
+#define HL_SCHED_PAIRS 4u     /* bulk kernel with two adjacent sites per lane (vector loads/stores);
+                                 ignored with HL_SCHED_FUSED */
 
 typedef struct hl_ctx hl_ctx;
 
@@ -291,7 +303,7 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes);
  * around the trials. */
 int hl_autotune(hl_ctx *ctx, int budget_ms);
 int hl_get_schedule(hl_ctx *ctx, int32_t *block_size, int32_t *flags);
-/* block_size in {64, 128, 256, 512, 1024}; flags of HL_SCHED_*. */
+/* block_size in {64, 128, 256}; flags of HL_SCHED_*. */
 int hl_set_schedule(hl_ctx *ctx, int32_t block_size, int32_t flags);
 
 /* Description of the committed context. */
@@ -300,7 +312,9 @@ int hl_get_info(hl_ctx *ctx, hl_info *out);
 /* Measurement: advance nsteps (1..100000) steps with plain launches and HIP
  * events recorded on the context stream around each kernel; return the mean
  * duration in milliseconds of the bulk-site kernel and of the boundary-site
- * kernel of one step.  The steps are real steps (t advances). */
+ * kernel of one step (with HL_SCHED_FUSED: 0 and the fused kernel).  The
+ * one-work-group finalize kernel is not included.  The steps are real steps
+ * (t advances). */
 int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd);
 
 #ifdef __cplusplus

@@ -37,6 +37,10 @@ HL_SCHED_XCD_REMAP = 1
 HL_ORDER_BULK_MORTON = 1
 HL_ORDER_BOUNDARY_MORTON = 2
 HL_ORDER_INTERLEAVE = 4
+HL_ORDER_BRICK = 8
+HL_SCHED_FUSED = 2
+HL_SCHED_PAIRS = 4
+HL_SCHEME_AA = 16
 
 
 class hl_info(ct.Structure):

@@ -98,6 +98,8 @@ struct Range {
 struct hl_ctx {
     int device = 0, precision = 0;
     uint64_t order_flags = 0;
+    bool aa = false;          // in-place AA-pattern scheme
+    int64_t stats_t = -1;     // step whose iolet means / boundary values are on the device
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     std::string err;
@@ -112,9 +114,10 @@ struct hl_ctx {
     int64_t t_host = 0;
     // layout
     int64_t N = 0, NB = 0, IO0 = 0, Nb = 0, Nio = 0;
+    int64_t n_sites = 0, n_bulk_sites = 0, n_io_sites = 0;
     std::vector<Range> ranges;
     std::vector<uint8_t> site_wall;  // interleaved layout: 1 where a site has a boundary link
-    std::vector<hl::Entry> entries;
+    std::vector<hl::Entry> entries, entries2;
     int n_bulk_blocks = 0, n_bnd_blocks = 0;
     std::vector<hl::SegDev> hseg;
     std::vector<hl::IoletDev> hio;
@@ -125,7 +128,7 @@ struct hl_ctx {
     float *d_bq = nullptr;
     double *d_bphi = nullptr, *d_bnrm = nullptr;
     void *d_up[2] = {nullptr, nullptr};
-    hl::Entry *d_entries = nullptr;
+    hl::Entry *d_entries = nullptr, *d_entries2 = nullptr;
     hl::SegDev *d_seg = nullptr;
     hl::IoletDev *d_io = nullptr;
     hl::PairDev *d_pairs = nullptr;
@@ -191,7 +194,7 @@ void free_device(hl_ctx *c) {
     c->gexec = nullptr;
     c->graph_steps = 0;
     void *ps[] = {c->lat[0], c->lat[1], c->d_src, c->d_bq, c->d_bphi, c->d_bnrm, c->d_up[0], c->d_up[1],
-                  c->d_entries, c->d_seg, c->d_io, c->d_pairs, c->d_ctrl, c->d_partials, c->d_stats,
+                  c->d_entries, c->d_entries2, c->d_seg, c->d_io, c->d_pairs, c->d_ctrl, c->d_partials, c->d_stats,
                   c->d_bc, c->d_held, c->d_obs, c->d_fbuf};
     for (void *p : ps) dfree(p);
     for (auto &d : c->doms) {
@@ -204,6 +207,7 @@ void free_device(hl_ctx *c) {
     c->d_bphi = c->d_bnrm = nullptr;
     c->d_up[0] = c->d_up[1] = nullptr;
     c->d_entries = nullptr;
+    c->d_entries2 = nullptr;
     c->d_seg = nullptr;
     c->d_io = nullptr;
     c->d_pairs = nullptr;
@@ -239,6 +243,9 @@ hl::KArgs make_args(hl_ctx *c) {
     a.up1 = c->d_up[1];
     a.bnrm = c->d_bnrm;
     a.entries = c->d_entries;
+    a.entries2 = c->d_entries2;
+    a.n_pairs_blocks = ((c->sched_flags & HL_SCHED_PAIRS) && !(c->sched_flags & HL_SCHED_FUSED))
+                           ? (int32_t)c->entries2.size() : 0;
     a.seg = c->d_seg;
     a.io = c->d_io;
     a.pairs = c->d_pairs;
@@ -247,6 +254,7 @@ hl::KArgs make_args(hl_ctx *c) {
     a.couple_mode = c->couple_mode;
     a.xcd_remap = (c->sched_flags & HL_SCHED_XCD_REMAP) ? 1 : 0;
     a.ctrl = c->d_ctrl;
+    a.aa = c->aa ? 1 : 0;
     a.partials = c->d_partials;
     a.stats = c->d_stats;
     a.bc = c->d_bc;
@@ -260,7 +268,8 @@ hl::KArgs make_args(hl_ctx *c) {
 // Split the class ranges into work-group entries of at most `block` sites:
 // entries for the bulk kernel first, then those for the boundary kernel.  In
 // the interleaved layout a chunk of a mixed range goes to the bulk kernel
-// when none of its sites has a boundary link.
+// when none of its sites has a boundary link.  The fused schedule keeps every
+// entry in storage order for a single launch (n_bulk_blocks = 0).
 constexpr int32_t K_MIXED = 3;
 
 void build_entries(hl_ctx *c) {
@@ -279,7 +288,7 @@ void build_entries(hl_ctx *c) {
                 for (int32_t k = 0; k < e.count && !wall; ++k) wall = c->site_wall[(size_t)e.start + k] != 0;
                 e.tag = wall ? hl::K_WALL : hl::K_BULK;
             }
-            if ((e.tag & 3) == hl::K_BULK)
+            if ((e.tag & 3) == hl::K_BULK && !(c->sched_flags & HL_SCHED_FUSED))
                 bulk.push_back(e);
             else
                 bnd.push_back(e);
@@ -287,6 +296,18 @@ void build_entries(hl_ctx *c) {
     }
     c->entries = bulk;
     c->entries.insert(c->entries.end(), bnd.begin(), bnd.end());
+    c->entries2.clear();
+    for (const hl::Entry &e : bulk) {
+        // merge consecutive bulk entries of one range into chunks of 2 x block
+        if (!c->entries2.empty()) {
+            hl::Entry &l = c->entries2.back();
+            if (l.seg == e.seg && l.start + l.count == e.start && l.count + e.count <= 2 * c->block) {
+                l.count += e.count;
+                continue;
+            }
+        }
+        c->entries2.push_back(e);
+    }
     c->n_bulk_blocks = (int)bulk.size();
     c->n_bnd_blocks = (int)bnd.size();
     for (int e = 0; e < (int)c->entries.size(); ++e) {
@@ -300,11 +321,17 @@ void build_entries(hl_ctx *c) {
 
 int upload_schedule(hl_ctx *c) {
     dfree(c->d_entries);
+    dfree(c->d_entries2);
     dfree(c->d_partials);
     c->d_entries = nullptr;
+    c->d_entries2 = nullptr;
     c->d_partials = nullptr;
     int rc;
     if ((rc = dalloc(c, &c->d_entries, c->entries.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_entries2, c->entries2.size())) != HL_OK) return rc;
+    if (!c->entries2.empty())
+        HIPC(c, hipMemcpy(c->d_entries2, c->entries2.data(), c->entries2.size() * sizeof(hl::Entry),
+                          hipMemcpyHostToDevice));
     if ((rc = dalloc(c, &c->d_partials, 2 * c->entries.size())) != HL_OK) return rc;
     HIPC(c, hipMemcpy(c->d_entries, c->entries.data(), c->entries.size() * sizeof(hl::Entry),
                       hipMemcpyHostToDevice));
@@ -316,10 +343,15 @@ int upload_schedule(hl_ctx *c) {
     return HL_OK;
 }
 
-int launch_steps_plain(hl_ctx *c, int64_t n, hipStream_t st) {
+// n steps as plain launches; t0 is the step counter before the first one (the
+// in-place scheme alternates its even and odd kernels).
+int launch_steps_plain(hl_ctx *c, int64_t n, hipStream_t st, int64_t t0) {
     const hl::KArgs a = make_args(c);
+    const bool fused = (c->sched_flags & HL_SCHED_FUSED) != 0;
     for (int64_t k = 0; k < n; ++k) {
-        int e = hl::launch_step(c->precision, a, c->n_bulk_blocks, c->n_bnd_blocks, c->block, st);
+        int e = c->aa ? hl::launch_aa_step(c->precision, a, c->n_bulk_blocks, c->n_bnd_blocks, c->block, st, 0, fused,
+                                           (int)((t0 + k) & 1))
+                      : hl::launch_step(c->precision, a, c->n_bulk_blocks, c->n_bnd_blocks, c->block, st, 0, fused);
         if (e != 0) return fail(c, HL_E_DEVICE, "step launch failed: %s", hipGetErrorString((hipError_t)e));
     }
     return HL_OK;
@@ -331,7 +363,7 @@ int ensure_graph(hl_ctx *c) {
     c->gexec = nullptr;
     if (!c->cap_stream) HIPC(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIPC(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = launch_steps_plain(c, c->steps_per_graph, c->cap_stream);
+    int rc = launch_steps_plain(c, c->steps_per_graph, c->cap_stream, 0);  // replayed from even steps only
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (rc != HL_OK) {
@@ -347,19 +379,28 @@ int ensure_graph(hl_ctx *c) {
 }
 
 int run_steps(hl_ctx *c, int64_t n) {
-    int64_t rest = n;
-    if (c->drive == HL_DRIVE_GRAPH && n >= c->steps_per_graph) {
+    int64_t rest = n, t = c->t_host;
+    if (c->aa && (c->steps_per_graph & 1)) c->steps_per_graph *= 2;  // graphs keep the sweep parity
+    if (c->drive == HL_DRIVE_GRAPH && n >= c->steps_per_graph + (t & 1)) {
+        if (c->aa && (t & 1)) {
+            int rc = launch_steps_plain(c, 1, c->stream, t);
+            if (rc != HL_OK) return rc;
+            ++t;
+            --rest;
+        }
         int rc = ensure_graph(c);
         if (rc != HL_OK) return rc;
         while (rest >= c->graph_steps) {
             HIPC(c, hipGraphLaunch(c->gexec, c->stream));
             rest -= c->graph_steps;
+            t += c->graph_steps;
         }
     }
-    int rc = launch_steps_plain(c, rest, c->stream);
+    int rc = launch_steps_plain(c, rest, c->stream, t);
     if (rc != HL_OK) return rc;
     c->t_host += n;
     c->obs_t = -1;
+    c->stats_t = c->aa ? c->t_host - 1 : c->t_host;
     HIPC(c, hipMemcpyAsync(c->h_nan, &c->d_ctrl->nan_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     return HL_OK;
 }
@@ -422,9 +463,31 @@ int observe(hl_ctx *c, bool with_f) {
 // and boundary values of step t.
 int reinit(hl_ctx *c) {
     hl::KArgs a = make_args(c);
-    int e = hl::launch_init(c->precision, a, (int)c->entries.size(), c->block, c->stream);
+    int e;
+    if (c->aa) {
+        // the lattice holds f(t) in natural slots: mark it and take its moments
+        HIPC(c, hipStreamSynchronize(c->stream));
+        const int one = 1;
+        HIPC(c, hipMemcpy(&c->d_ctrl->direct, &one, sizeof one, hipMemcpyHostToDevice));
+        e = hl::launch_aa_moments(c->precision, a, (int)c->entries.size(), c->block, c->stream, (int)(c->t_host & 1));
+    } else {
+        e = hl::launch_init(c->precision, a, (int)c->entries.size(), c->block, c->stream);
+    }
     if (e != 0) return fail(c, HL_E_DEVICE, "init launch failed: %s", hipGetErrorString((hipError_t)e));
     c->obs_t = -1;
+    c->stats_t = c->t_host;
+    return HL_OK;
+}
+
+// The in-place scheme reduces f(t) during the sweep t -> t+1; a read of the
+// iolet means or boundary values of the current step runs the moments pass
+// (idempotent: the next sweep recomputes the same values).
+int ensure_stats(hl_ctx *c) {
+    if (c->stats_t == c->t_host) return HL_OK;
+    hl::KArgs a = make_args(c);
+    int e = hl::launch_aa_moments(c->precision, a, (int)c->entries.size(), c->block, c->stream, (int)(c->t_host & 1));
+    if (e != 0) return fail(c, HL_E_DEVICE, "moments launch failed: %s", hipGetErrorString((hipError_t)e));
+    c->stats_t = c->t_host;
     return HL_OK;
 }
 
@@ -456,12 +519,22 @@ int commit(hl_ctx *c) {
             cls[d][x] = k >= 0 ? k : (wall ? -2 : -1);
         }
     }
+    c->n_sites = total;
+    c->n_bulk_sites = 0;
+    c->n_io_sites = 0;
+    for (int d = 0; d < D; ++d)
+        for (auto v : cls[d]) {
+            if (v == -1) ++c->n_bulk_sites;
+            if (v >= 0) ++c->n_io_sites;
+        }
     // internal order: bulk, wall, iolet groups; inside a group caller order or
     // Morton order of the coordinates
     c->ranges.clear();
     int64_t pos = 0;
+    auto align4 = [&]() { pos = (pos + 3) & ~(int64_t)3; };
     auto place = [&](int d, int32_t key, bool morton) {
         Domain &dm = c->doms[d];
+        align4();
         std::vector<int64_t> idx;
         for (int64_t x = 0; x < dm.n; ++x)
             if (cls[d][x] == key) idx.push_back(x);
@@ -483,7 +556,44 @@ int commit(hl_ctx *c) {
     const bool mb = (c->order_flags & HL_ORDER_BULK_MORTON) != 0;
     const bool mw = (c->order_flags & HL_ORDER_BOUNDARY_MORTON) != 0;
     const bool inter = (c->order_flags & HL_ORDER_INTERLEAVE) != 0;
-    if (inter) {
+    const bool brick = (c->order_flags & HL_ORDER_BRICK) != 0;
+    if (brick) {
+        // per domain: bricks in lexicographic brick order; inside a brick the
+        // bulk sites, then the wall sites, each in lexicographic order
+        c->site_wall.clear();
+        for (int d = 0; d < D; ++d) {
+            Domain &dm = c->doms[d];
+            dm.c2g.assign(dm.n, -1);
+            std::vector<std::pair<uint64_t, int64_t>> kv;
+            int64_t mn[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+            for (int64_t x = 0; x < dm.n; ++x)
+                for (int a = 0; a < 3; ++a) mn[a] = std::min<int64_t>(mn[a], dm.coords[(size_t)a * dm.n + x]);
+            for (int64_t x = 0; x < dm.n; ++x) {
+                const int32_t k = cls[d][x];
+                if (k >= 0) continue;
+                const uint64_t px = (uint64_t)(dm.coords[x] - mn[0]);
+                const uint64_t py = (uint64_t)(dm.coords[(size_t)dm.n + x] - mn[1]);
+                const uint64_t pz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] - mn[2]);
+                const uint64_t bkey = ((pz >> 4) << 42) | ((py >> 4) << 21) | (px >> 4);
+                const uint64_t lkey = ((pz & 15) << 8) | ((py & 15) << 4) | (px & 15);
+                const uint64_t wall = (k == -2) ? 1 : 0;
+                kv.push_back({(bkey << 13) | (wall << 12) | lkey, x});
+            }
+            std::sort(kv.begin(), kv.end());
+            size_t m = 0;
+            while (m < kv.size()) {
+                const uint64_t grp = kv[m].first >> 12;  // brick and class
+                align4();
+                const int64_t st = pos;
+                while (m < kv.size() && (kv[m].first >> 12) == grp) {
+                    dm.c2g[kv[m].second] = pos++;
+                    ++m;
+                }
+                c->ranges.push_back({st, pos - st, d, (grp & 1) ? hl::K_WALL : hl::K_BULK});
+            }
+        }
+        c->NB = 0;
+    } else if (inter) {
         // bulk and wall sites together, in one range per domain
         for (int d = 0; d < D; ++d) {
             for (auto &v : cls[d])
@@ -495,6 +605,7 @@ int commit(hl_ctx *c) {
             std::vector<int32_t> saved = cd;
             for (auto &v : cd)
                 if (v == -3) v = -1;
+            align4();
             const int64_t st = pos;
             place(d, -1, mb);
             cd = saved;
@@ -511,20 +622,25 @@ int commit(hl_ctx *c) {
     } else {
         for (int d = 0; d < D; ++d) {
             c->doms[d].c2g.assign(c->doms[d].n, -1);
+            align4();
             const int64_t st = pos;
             if (place(d, -1, mb) > 0) c->ranges.push_back({st, pos - st, d, hl::K_BULK});
         }
+        align4();
         c->NB = pos;
         for (int d = 0; d < D; ++d) {
+            align4();
             const int64_t st = pos;
             if (place(d, -2, mw) > 0) c->ranges.push_back({st, pos - st, d, hl::K_WALL});
         }
     }
+    align4();
     c->IO0 = pos;
     std::vector<int64_t> io_lo(io_count, 0), io_n(io_count, 0);
     for (int d = 0; d < D; ++d) {
         Domain &dm = c->doms[d];
         for (int k = 0; k < dm.n_iolet; ++k) {
+            align4();
             const int64_t st = pos;
             place(d, k, mw);
             io_lo[dm.io_base + k] = st;
@@ -532,7 +648,8 @@ int commit(hl_ctx *c) {
             if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_IOLET | ((dm.io_base + k) << 2)});
         }
     }
-    c->N = pos;
+    align4();
+    c->N = pos;  // padded: every range starts, and N ends, on a multiple of 4 slots
     c->Nb = c->N - c->NB;
     c->Nio = c->N - c->IO0;
     const int64_t N = c->N, NB = c->NB, Nb = c->Nb, Nio = c->Nio;
@@ -658,8 +775,10 @@ int commit(hl_ctx *c) {
     const size_t S = store_bytes(c->precision), A = arith_bytes(c->precision);
     int rc;
     for (int p = 0; p < 2; ++p) {
-        HIPC(c, hipMalloc(&c->lat[p], (size_t)Q * N * S));
-        c->dev_bytes += (int64_t)((size_t)Q * N * S);
+        if (p == 0 || !c->aa) {
+            HIPC(c, hipMalloc(&c->lat[p], (size_t)Q * N * S));
+            c->dev_bytes += (int64_t)((size_t)Q * N * S);
+        }
         HIPC(c, hipMalloc(&c->d_up[p], std::max<size_t>((size_t)3 * Nio * A, 8)));
         c->dev_bytes += (int64_t)std::max<size_t>((size_t)3 * Nio * A, 8);
     }
@@ -767,7 +886,8 @@ struct StateHeader {
 size_t state_bytes(hl_ctx *c) {
     const size_t S = store_bytes(c->precision), A = arith_bytes(c->precision);
     const size_t nio = c->hio.size();
-    return sizeof(StateHeader) + sizeof(hl::Ctrl) + 2 * (size_t)Q * c->N * S + 2 * (size_t)3 * c->Nio * A +
+    const size_t nlat = c->aa ? 1 : 2;
+    return sizeof(StateHeader) + sizeof(hl::Ctrl) + nlat * (size_t)Q * c->N * S + 2 * (size_t)3 * c->Nio * A +
            (2 + 2 + 1) * nio * sizeof(double);
 }
 
@@ -799,7 +919,9 @@ int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     if (!out) return HL_E_INVAL;
     *out = nullptr;
     if (precision < HL_F64 || precision > HL_F16_OFFSET) return HL_E_INVAL;
-    if (flags & ~(uint64_t)(HL_ORDER_BULK_MORTON | HL_ORDER_BOUNDARY_MORTON | HL_ORDER_INTERLEAVE)) return HL_E_INVAL;
+    if (flags & ~(uint64_t)(HL_ORDER_BULK_MORTON | HL_ORDER_BOUNDARY_MORTON | HL_ORDER_INTERLEAVE | HL_ORDER_BRICK |
+                            HL_SCHEME_AA))
+        return HL_E_INVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HL_E_DEVICE;
     hipDeviceProp_t prop;
@@ -810,6 +932,7 @@ int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     c->device = device;
     c->precision = precision;
     c->order_flags = flags;
+    c->aa = (flags & HL_SCHEME_AA) != 0;
     if (hipHostMalloc((void **)&c->h_nan, sizeof(int), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return HL_E_NOMEM;
@@ -1088,7 +1211,9 @@ int hl_set_populations(hl_ctx *ctx, int32_t dom, const double *f) {
     *ctx->h_nan = 0;
     hl::KArgs a = make_args(ctx);
     a.fin = ctx->d_fbuf;
-    int e = hl::launch_load_raw(ctx->precision, a, ctx->stream);
+    int e = (ctx->aa && (ctx->t_host & 1))
+                ? hl::launch_aa_load_odd(ctx->precision, a, (int)ctx->entries.size(), ctx->block, ctx->stream)
+                : hl::launch_load_raw(ctx->precision, a, ctx->stream);
     if (e != 0) return fail(ctx, HL_E_DEVICE, "load launch failed: %s", hipGetErrorString((hipError_t)e));
     if ((rc = reinit(ctx)) != HL_OK) return rc;
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
@@ -1103,6 +1228,7 @@ int hl_read_iolet_stats(hl_ctx *ctx, int32_t dom, double *mean_u, double *mean_p
     if (d.n_iolet == 0) return HL_OK;
     if (!mean_u || !mean_p) return fail(ctx, HL_E_INVAL, "NULL output");
     HIPC(ctx, hipSetDevice(ctx->device));
+    if (ctx->aa && (rc = ensure_stats(ctx)) != HL_OK) return rc;
     const size_t nio = ctx->hio.size();
     std::vector<double> st(2 * nio);
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
@@ -1124,6 +1250,7 @@ int hl_read_iolet_bc(hl_ctx *ctx, int32_t dom, int which, double *out) {
     if (d.n_iolet == 0) return HL_OK;
     if (!out) return fail(ctx, HL_E_INVAL, "NULL output");
     HIPC(ctx, hipSetDevice(ctx->device));
+    if (ctx->aa && which == 0 && (rc = ensure_stats(ctx)) != HL_OK) return rc;
     const size_t nio = ctx->hio.size();
     std::vector<double> bc(2 * nio);
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
@@ -1174,7 +1301,7 @@ int hl_get_state(hl_ctx *ctx, void *buf, size_t *bytes) {
     StateHeader h{};
     std::memcpy(h.magic, "HLSTATE", 8);
     h.version = 1;
-    h.precision = ctx->precision;
+    h.precision = ctx->precision | (ctx->aa ? 0x100 : 0);
     h.N = ctx->N;
     h.Nio = ctx->Nio;
     h.n_io = (int64_t)ctx->hio.size();
@@ -1184,7 +1311,7 @@ int hl_get_state(hl_ctx *ctx, void *buf, size_t *bytes) {
     const size_t S = store_bytes(ctx->precision), A = arith_bytes(ctx->precision), nio = ctx->hio.size();
     HIPC(ctx, hipMemcpy(p, ctx->d_ctrl, sizeof(hl::Ctrl), hipMemcpyDeviceToHost));
     p += sizeof(hl::Ctrl);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < (ctx->aa ? 1 : 2); ++k) {
         HIPC(ctx, hipMemcpy(p, ctx->lat[k], (size_t)Q * ctx->N * S, hipMemcpyDeviceToHost));
         p += (size_t)Q * ctx->N * S;
     }
@@ -1210,7 +1337,8 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes) {
     std::memcpy(&h, buf, sizeof h);
     if (std::memcmp(h.magic, "HLSTATE", 8) != 0 || h.version != 1)
         return fail(ctx, HL_E_INVAL, "not a state buffer of this library version");
-    if (bytes != need || h.bytes != (int64_t)need || h.precision != ctx->precision || h.N != ctx->N ||
+    if (bytes != need || h.bytes != (int64_t)need || h.precision != (ctx->precision | (ctx->aa ? 0x100 : 0)) ||
+        h.N != ctx->N ||
         h.Nio != ctx->Nio || h.n_io != (int64_t)ctx->hio.size())
         return fail(ctx, HL_E_INVAL, "state layout does not match this context");
     HIPC(ctx, hipSetDevice(ctx->device));
@@ -1221,7 +1349,7 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes) {
     std::memcpy(&ctrl, p, sizeof ctrl);
     HIPC(ctx, hipMemcpy(ctx->d_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
     p += sizeof(hl::Ctrl);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < (ctx->aa ? 1 : 2); ++k) {
         HIPC(ctx, hipMemcpy(ctx->lat[k], p, (size_t)Q * ctx->N * S, hipMemcpyHostToDevice));
         p += (size_t)Q * ctx->N * S;
     }
@@ -1237,6 +1365,7 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes) {
     ctx->t_host = ctrl.t;
     *ctx->h_nan = ctrl.nan_flag;
     ctx->obs_t = -1;
+    ctx->stats_t = ctx->aa ? -1 : ctx->t_host;
     return HL_OK;
 }
 
@@ -1251,8 +1380,9 @@ int hl_set_schedule(hl_ctx *ctx, int32_t block_size, int32_t flags) {
     if (!ctx) return HL_E_INVAL;
     if (block_size != 64 && block_size != 128 && block_size != 256)
         return fail(ctx, HL_E_INVAL, "block size %d not in {64, 128, 256}", block_size);
-    if (flags & ~(int32_t)HL_SCHED_XCD_REMAP) return fail(ctx, HL_E_INVAL, "unknown schedule flags");
-    const bool rebuild = block_size != ctx->block;
+    if (flags & ~(int32_t)(HL_SCHED_XCD_REMAP | HL_SCHED_FUSED | HL_SCHED_PAIRS))
+        return fail(ctx, HL_E_INVAL, "unknown schedule flags");
+    const bool rebuild = block_size != ctx->block || ((flags ^ ctx->sched_flags) & HL_SCHED_FUSED);
     ctx->block = block_size;
     ctx->sched_flags = flags;
     if (!ctx->committed) return HL_OK;
@@ -1283,7 +1413,9 @@ int hl_autotune(hl_ctx *ctx, int budget_ms) {
     struct Cand { int block, flags; double ms; };
     std::vector<Cand> cands;
     for (int b : {64, 128, 256})
-        for (int f : {0, (int)HL_SCHED_XCD_REMAP}) cands.push_back({b, f, 0.0});
+        for (int f : {0, (int)HL_SCHED_XCD_REMAP, (int)HL_SCHED_FUSED, (int)(HL_SCHED_FUSED | HL_SCHED_XCD_REMAP),
+                      (int)HL_SCHED_PAIRS, (int)(HL_SCHED_PAIRS | HL_SCHED_XCD_REMAP)})
+            cands.push_back({b, f, 0.0});
     hipEvent_t e0, e1;
     HIPC(ctx, hipEventCreate(&e0));
     HIPC(ctx, hipEventCreate(&e1));
@@ -1330,16 +1462,24 @@ int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd
     std::vector<hipEvent_t> ev((size_t)3 * nsteps, nullptr);
     for (auto &e : ev) HIPC(ctx, hipEventCreate(&e));
     const hl::KArgs a = make_args(ctx);
+    const bool fu = (ctx->sched_flags & HL_SCHED_FUSED) != 0;
     int err = 0;
+    auto part = [&](int64_t k, int which) {
+        const int odd = (int)((ctx->t_host + k) & 1);
+        return ctx->aa ? hl::launch_aa_step(ctx->precision, a, ctx->n_bulk_blocks, ctx->n_bnd_blocks, ctx->block,
+                                            ctx->stream, which, fu, odd)
+                       : hl::launch_step(ctx->precision, a, ctx->n_bulk_blocks, ctx->n_bnd_blocks, ctx->block,
+                                         ctx->stream, which, fu);
+    };
     for (int64_t k = 0; k < nsteps && !err; ++k) {
         HIPC(ctx, hipEventRecord(ev[3 * k], ctx->stream));
-        err = hl::launch_step(ctx->precision, a, ctx->n_bulk_blocks, ctx->n_bnd_blocks, ctx->block, ctx->stream, 1);
+        err = part(k, 1);
         HIPC(ctx, hipEventRecord(ev[3 * k + 1], ctx->stream));
-        if (!err)
-            err = hl::launch_step(ctx->precision, a, ctx->n_bulk_blocks, ctx->n_bnd_blocks, ctx->block, ctx->stream, 2);
+        if (!err) err = part(k, 2);
         HIPC(ctx, hipEventRecord(ev[3 * k + 2], ctx->stream));
+        if (!err) err = part(k, 3);
     }
-    HIPC(ctx, hipEventSynchronize(ev.back()));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
     double sb = 0.0, sn = 0.0;
     for (int64_t k = 0; k < nsteps; ++k) {
         float m1 = 0.0f, m2 = 0.0f;
@@ -1352,6 +1492,7 @@ int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd
     if (err) return fail(ctx, HL_E_DEVICE, "step launch failed: %s", hipGetErrorString((hipError_t)err));
     ctx->t_host += nsteps;
     ctx->obs_t = -1;
+    ctx->stats_t = ctx->aa ? ctx->t_host - 1 : ctx->t_host;
     *ms_bulk = sb / (double)nsteps;
     *ms_bnd = sn / (double)nsteps;
     return HL_OK;
@@ -1362,10 +1503,10 @@ int hl_get_info(hl_ctx *ctx, hl_info *out) {
     int rc = commit(ctx);
     if (rc) return rc;
     std::memset(out, 0, sizeof *out);
-    out->n_sites = ctx->N;
-    out->n_bulk = ctx->NB;
-    out->n_boundary = ctx->Nb;
-    out->n_iolet_sites = ctx->Nio;
+    out->n_sites = ctx->n_sites;
+    out->n_bulk = ctx->n_bulk_sites;
+    out->n_boundary = ctx->n_sites - ctx->n_bulk_sites;
+    out->n_iolet_sites = ctx->n_io_sites;
     out->n_domains = (int32_t)ctx->doms.size();
     out->n_iolets = (int32_t)ctx->hio.size();
     out->n_blocks_bulk = ctx->n_bulk_blocks;
@@ -1375,7 +1516,9 @@ int hl_get_info(hl_ctx *ctx, hl_info *out) {
     out->sched_flags = ctx->sched_flags;
     out->drive = ctx->drive;
     out->device_bytes = ctx->dev_bytes;
-    out->bytes_per_site = 2.0 * Q * (double)store_bytes(ctx->precision) + 18.0 * 4.0;
+    // two-lattice: 19 reads + 19 writes + 18 int32 indices per step; in-place:
+    // the same on odd steps, no indices on even steps
+    out->bytes_per_site = 2.0 * Q * (double)store_bytes(ctx->precision) + (ctx->aa ? 9.0 : 18.0) * 4.0;
     return HL_OK;
 }
 

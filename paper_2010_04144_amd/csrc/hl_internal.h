@@ -85,6 +85,9 @@ struct KArgs {
     const PairDev *pairs;
     int32_t n_io, n_pairs;
     int32_t couple_mode, xcd_remap;
+    const Entry *entries2;   // bulk entries of 2 x block sites (two sites per lane)
+    int32_t aa;              // 1: one in-place lattice (lat0), AA-pattern sweeps
+    int32_t n_pairs_blocks;  // > 0: the bulk launch runs the two-sites-per-lane kernel
     Ctrl *ctrl;
     double *partials;  // [2][n_entries]
     double *stats;     // [2][n_io]: mean u.n, mean rho
@@ -96,13 +99,22 @@ struct KArgs {
 };
 
 // Kernel launchers (hl_kernels.hip).  Each returns a hipError_t value.
-// part: 0 = every launch of a step, 1 = the bulk-site launch only, 2 = the
-// boundary-site launch and the finalize only.
-int launch_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part = 0);
+// part: 0 = every launch of a step, 1 = the bulk-site kernel, 2 = the
+// boundary-site (or fused) kernel, 3 = the finalize kernel.
+// fused: one launch over all n_bnd entries (storage order), each work-group
+// choosing the bulk or the boundary path from its entry class.
+int launch_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part = 0,
+                bool fused = false);
 int launch_init(int prec, const KArgs &a, int n_entries, int block, void *stream);
 int launch_observe(int prec, const KArgs &a, int n_entries, int block, void *stream);
 int launch_load_raw(int prec, const KArgs &a, void *stream);
 int launch_fill_rest(int prec, const KArgs &a, void *stream);
 int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *out, void *stream);
+// In-place (AA-pattern) scheme: one sweep t -> t+1 (odd = t & 1), and the
+// moments-only pass that computes the iolet means and boundary values of t.
+int launch_aa_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part, bool fused,
+                   int odd);
+int launch_aa_moments(int prec, const KArgs &a, int n_entries, int block, void *stream, int odd);
+int launch_aa_load_odd(int prec, const KArgs &a, int n_entries, int block, void *stream);
 
 }  // namespace hl

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "hl_internal.h"
 
 namespace hl {
@@ -197,9 +199,15 @@ __device__ double series_at(const IoletDev &io, int64_t t) {
 // fences): iolet means of f(tn) from the per-work-group partial sums,
 // coupling, boundary values for the stream tn -> tn+1, then publish tn.
 // raw = 1 after a (re)initialisation, where tn = t.
-__global__ void __launch_bounds__(256) k_finalize(KArgs a, int raw) {
+// mode: FIN_STEP (two-lattice step: f(t+1) was reduced; t := t+1),
+// FIN_RAW (two-lattice reinitialisation: f(t) reduced; t kept; direct := 1),
+// FIN_AA_SWEEP (in-place sweep: f(t) reduced; t := t+1),
+// FIN_AA_MOMENTS (moments-only pass: f(t) reduced; t kept).
+enum { FIN_STEP = 0, FIN_RAW = 1, FIN_AA_SWEEP = 2, FIN_AA_MOMENTS = 3 };
+
+__global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
     const int64_t t = a.ctrl->t;
-    const int64_t tn = raw ? t : t + 1;
+    const int64_t tn = (mode == FIN_STEP) ? t + 1 : t;
     double *mu = a.stats;
     double *mr = a.stats + a.n_io;
     for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
@@ -243,12 +251,59 @@ __global__ void __launch_bounds__(256) k_finalize(KArgs a, int raw) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        a.ctrl->direct = raw;
-        a.ctrl->t = tn;
+        if (mode == FIN_STEP || mode == FIN_RAW) {
+            a.ctrl->direct = (mode == FIN_RAW);
+            a.ctrl->t = tn;
+        } else if (mode == FIN_AA_SWEEP) {
+            a.ctrl->direct = 0;
+            a.ctrl->t = t + 1;
+        }
     }
 }
 
-enum { M_BULK = 0, M_BND = 1, M_RAW = 2 };
+// Moments and LBGK collision with Guo forcing for one site: x holds f(t)
+// (or its offset) on entry and f*(t) on exit; returns true when the density
+// is not finite.
+template <typename R, bool OFF>
+__device__ __forceinline__ bool collide_site(R (&x)[Q], const SegDev &sg, R Fx, R Fy, R Fz) {
+    R m0 = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        m0 += x[i];
+        if (CX[i]) jx += R(CX[i]) * x[i];
+        if (CY[i]) jy += R(CY[i]) * x[i];
+        if (CZ[i]) jz += R(CZ[i]) * x[i];
+    }
+    R rho, drho = 0;
+    if (OFF) {
+        drho = m0;
+        rho = R(RHO0) + drho;
+    } else {
+        rho = m0;
+    }
+    const R ux = (jx + R(0.5) * Fx) / rho;
+    const R uy = (jy + R(0.5) * Fy) / rho;
+    const R uz = (jz + R(0.5) * Fz) / rho;
+    const R it = (R)sg.inv_tau;
+    const R uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+        const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+        const R eq = OFF ? wgt<R>(i) * (drho + rho * poly) : wgt<R>(i) * rho * (R(1) + poly);
+        R o = x[i] - (x[i] - eq) * it;
+        if (sg.has_force) {
+            const R sF = (R(3) * (R(CX[i]) - ux) + R(9) * cu * R(CX[i])) * Fx +
+                         (R(3) * (R(CY[i]) - uy) + R(9) * cu * R(CY[i])) * Fy +
+                         (R(3) * (R(CZ[i]) - uz) + R(9) * cu * R(CZ[i])) * Fz;
+            o += (R)sg.guo_pref * wgt<R>(i) * sF;
+        }
+        x[i] = o;
+    }
+    return !isfinite(rho);
+}
+
+enum { M_BULK = 0, M_BND = 1, M_RAW = 2, M_FUSED = 3 };
 
 // ---------------------------------------------------------------------------
 // The step kernel.  M_BULK / M_BND: pull step t -> t+1 over bulk or boundary
@@ -256,7 +311,7 @@ enum { M_BULK = 0, M_BND = 1, M_RAW = 2 };
 // (initialisation and population loads), without advancing t.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_step(KArgs a) {
+__device__ __forceinline__ void step_body(const KArgs &a) {
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     __shared__ double lds[8];
@@ -277,6 +332,11 @@ __global__ void __launch_bounds__(256) k_step(KArgs a) {
             const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
 #pragma unroll
             for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s);
+        } else if (MODE == M_FUSED) {
+            if (klass == K_BULK)
+                gather<T, false>(a, e, sg, t, s, x);
+            else
+                gather<T, true>(a, e, sg, t, s, x);
         } else {
             gather<T, MODE == M_BND>(a, e, sg, t, s, x);
         }
@@ -357,6 +417,373 @@ __global__ void __launch_bounds__(256) k_step(KArgs a) {
     }
 }
 
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_step(KArgs a) {
+    step_body<T, MODE>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Bulk sites, two adjacent sites per lane.  Range starts and N are multiples
+// of 4, so the pull indices, the rest population and the stores of a lane
+// move as aligned 2-element vectors; a gather moves as one vector (4-byte
+// alignment, so the compiler splits it where the target needs that) when the
+// two sources are adjacent, else as two loads.  Same arithmetic as the
+// one-site kernel.
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { typedef double elem; typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Vec2<float> { typedef float elem; typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct Vec2<__half> { typedef _Float16 elem; typedef _Float16 type __attribute__((ext_vector_type(2))); };
+typedef int32_t int2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double cvt(double v) { return v; }
+__device__ __forceinline__ float cvt(float v) { return v; }
+__device__ __forceinline__ float cvt(_Float16 v) { return (float)v; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
+    using R = typename Arith<T>::R;
+    using V2 = typename Vec2<T>::type;
+    using E = typename Vec2<T>::elem;
+    constexpr bool OFF = Arith<T>::OFF;
+    const int64_t t = a.ctrl->t;
+    const int64_t tn = t + 1;
+    const Entry e = a.entries2[block_index(a.xcd_remap)];
+    const SegDev &sg = a.seg[e.seg];
+    const int base = 2 * (int)threadIdx.x;
+    if (base >= e.count) return;
+    const bool two = base + 1 < e.count;
+    const int64_t s = (int64_t)e.start + base;
+    const int64_t N = a.N;
+    const T *__restrict__ lin = lat_ptr<T>(a, t);
+    T *__restrict__ lout = (T *)((tn & 1) ? a.lat1 : a.lat0);
+
+    R x0[Q], x1[Q];
+    if (two) {
+        const V2 v = *(const V2 *)(lin + s);
+        x0[0] = cvt(v.x);
+        x1[0] = cvt(v.y);
+    } else {
+        x0[0] = ldc(lin + s);
+        x1[0] = R(0);
+    }
+#pragma unroll
+    for (int j = 1; j < Q; ++j) {
+        const int32_t *sp = a.src + (size_t)(j - 1) * N + s;
+        const T *row = lin + (size_t)j * N;
+        if (two) {
+            const int2v sv = *(const int2v *)sp;
+            if (sv.y == sv.x + 1) {
+                V2 v;
+                __builtin_memcpy(&v, row + sv.x, sizeof(V2));
+                x0[j] = cvt(v.x);
+                x1[j] = cvt(v.y);
+            } else {
+                x0[j] = ldc(row + sv.x);
+                x1[j] = ldc(row + sv.y);
+            }
+        } else {
+            x0[j] = ldc(row + sp[0]);
+            x1[j] = R(0);
+        }
+    }
+    R Fx = 0, Fy = 0, Fz = 0;
+    if (sg.has_force) {
+        const double c = cos(sg.omega * (double)tn);
+        Fx = (R)(sg.F0[0] * c);
+        Fy = (R)(sg.F0[1] * c);
+        Fz = (R)(sg.F0[2] * c);
+    }
+    const bool bad0 = collide_site<R, OFF>(x0, sg, Fx, Fy, Fz);
+    const bool bad1 = two ? collide_site<R, OFF>(x1, sg, Fx, Fy, Fz) : false;
+    if (__ballot(bad0 || bad1) != 0 && (threadIdx.x & 63) == 0) a.ctrl->nan_flag = 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T *p = lout + (size_t)i * N + s;
+        if (two) {
+            V2 v;
+            v.x = (E)x0[i];
+            v.y = (E)x1[i];
+            __builtin_nontemporal_store(v, (V2 *)p);
+        } else {
+            stc(p, x0[i]);
+        }
+    }
+}
+
+// The same kernel with the register budget of six waves per SIMD: used for the
+// FP32/FP16 boundary and fused variants, whose boundary path would otherwise
+// drop occupancy to five waves (FP64 would spill, so it keeps k_step).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) k_step_occ(KArgs a) {
+    step_body<T, MODE>(a);
+}
+
+template <typename T, int MODE>
+static void launch_mode(int grid, int block, hipStream_t st, const KArgs &a) {
+    if constexpr (MODE == M_BULK) {
+        if (a.n_pairs_blocks > 0) {
+            hipLaunchKernelGGL((k_bulk2<T>), dim3(a.n_pairs_blocks), dim3(block), 0, st, a);
+            return;
+        }
+    }
+    if constexpr (std::is_same<T, double>::value || MODE == M_BULK || MODE == M_RAW)
+        hipLaunchKernelGGL((k_step<T, MODE>), dim3(grid), dim3(block), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_step_occ<T, MODE>), dim3(grid), dim3(block), 0, st, a);
+}
+
+// ===========================================================================
+// In-place (AA-pattern) streaming: one lattice A[19][N].
+//   even t: A holds f(t) in natural slots (A[i][x] = f_i(x)), except boundary
+//           slots left for a fixup by the previous odd sweep.  The even sweep
+//           reads its own slots, collides, and stores f*_i(x) into A[opp(i)][x]
+//           (swapped); halfway and Bouzidi q >= 1/2 wall values, which need
+//           only this site's f*, are stored there ready for the next read.
+//   odd t:  A holds f*(t-1) in swapped slots.  The odd sweep gathers
+//           f_j(x) = A[opp(j)][x - c_j], collides, and scatters f*_k(x) to
+//           A[k][x + c_k] (natural slots of the next step); a link whose
+//           destination is not fluid writes its boundary value (or the raw
+//           f*_k(x) when the rule needs data of another site or the boundary
+//           values of step t) into A[opp(k)][x].
+// Every slot is read and written by one thread only within a sweep, so a
+// sweep needs no second lattice.  The Bouzidi q < 1/2 interpolation, the
+// Ladd inlet term and the pressure-outlet equilibrium of the stream
+// t-1 -> t are applied when reading (they use step t-1's boundary values).
+// ===========================================================================
+template <typename T, bool BND, int ODD>
+__device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const SegDev &sg, int64_t t, int64_t s,
+                                        int direct, typename Arith<T>::R (&x)[Q], int32_t (&sr)[Q],
+                                        typename Arith<T>::R (&qv)[Q]) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    const T *__restrict__ A = (const T *)a.lat0;
+    const int64_t N = a.N;
+    // the pull table: needed by odd sweeps (gather/scatter) and by boundary sites
+    if (ODD || BND) {
+#pragma unroll
+        for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+    }
+    if (!ODD) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) x[i] = ldc(A + (size_t)i * N + s);
+    } else {
+        // (after a reload at an odd step the lattice holds f(t) in the same
+        // arrangement, so the same gather reads it back)
+        x[0] = ldc(A + s);
+#pragma unroll
+        for (int j = 1; j < Q; ++j) {
+            const int jb = opp(j);
+            if (BND)
+                x[j] = (sr[j] >= 0) ? ldc(A + (size_t)jb * N + sr[j]) : ldc(A + (size_t)j * N + s);
+            else
+                x[j] = ldc(A + (size_t)jb * N + sr[j]);
+        }
+    }
+    if (!BND) return;
+    const bool bz = sg.wall_mode == WALL_BOUZIDI;
+    const int64_t b = s - a.NB;
+#pragma unroll
+    for (int j = 1; j < Q; ++j) qv[j] = (bz && sr[j] == -1) ? (R)a.bq[(size_t)(j - 1) * a.Nb + b] : R(0.5);
+    if (direct) return;
+    // boundary rules of the stream t-1 -> t; x[j] holds f*_jb(s, t-1) (or a
+    // final value) for every direction whose upstream voxel is not fluid
+    const int64_t p = t - 1;
+    const int klass = e.tag & 3;
+    int kind = KIND_INLET;
+    R U = 0, nx = 0, ny = 0, nz = 0, phi = 0;
+    R rho_out = 0, drho_out = 0, ux = 0, uy = 0, uz = 0;
+    if (klass == K_IOLET) {
+        const int g = e.tag >> 2;
+        const IoletDev &io = a.io[g];
+        kind = io.kind;
+        const double v = a.bc[(p & 1) * a.n_io + g];
+        if (kind == KIND_INLET) {
+            U = (R)v;
+            nx = (R)io.nrm[0];
+            ny = (R)io.nrm[1];
+            nz = (R)io.nrm[2];
+            phi = (R)a.bphi[b];
+        } else {
+            rho_out = (R)v;
+            drho_out = (R)(v - RHO0);
+            const R *up = (const R *)((p & 1) ? a.up1 : a.up0);
+            const int64_t vi = s - a.IO0;
+            ux = up[vi];
+            uy = up[a.Nio + vi];
+            uz = up[2 * a.Nio + vi];
+        }
+    }
+#pragma unroll
+    for (int j = 1; j < Q; ++j) {
+        if (sr[j] >= 0) continue;
+        const int jb = opp(j);
+        if (sr[j] == -1) {
+            // halfway and q >= 1/2 values were stored final; q < 1/2 needs the
+            // second node x_s + c_j, whose population arrived as x[jb]
+            if (bz && qv[j] < R(0.5) && sr[jb] >= 0) x[j] = R(2) * qv[j] * x[j] + (R(1) - R(2) * qv[j]) * x[jb];
+        } else if (kind == KIND_INLET) {
+            const R cn = R(CX[jb]) * nx + R(CY[jb]) * ny + R(CZ[jb]) * nz;
+            x[j] = x[j] - R(6) * wgt<R>(j) * R(RHO0) * (cn * (U * phi));
+        } else {
+            const R cu = R(CX[j]) * ux + R(CY[j]) * uy + R(CZ[j]) * uz;
+            const R uu = ux * ux + uy * uy + uz * uz;
+            const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+            if (OFF)
+                x[j] = wgt<R>(j) * (drho_out + rho_out * poly);
+            else
+                x[j] = wgt<R>(j) * rho_out * (R(1) + poly);
+        }
+    }
+}
+
+// Moments of f(t) in x: iolet velocity history, partial sums of the iolet
+// work-groups, divergence flag.  Returns rho and u through the references.
+template <typename T>
+__device__ __forceinline__ void aa_moments(const KArgs &a, const Entry &e, int eidx, int64_t t, int64_t s, bool act,
+                                           const typename Arith<T>::R (&x)[Q], typename Arith<T>::R Fx,
+                                           typename Arith<T>::R Fy, typename Arith<T>::R Fz, double *lds) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    const int klass = e.tag & 3;
+    R rho = 1, ux = 0, uy = 0, uz = 0;
+    bool bad = false;
+    if (act) {
+        R m0 = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            m0 += x[i];
+            if (CX[i]) jx += R(CX[i]) * x[i];
+            if (CY[i]) jy += R(CY[i]) * x[i];
+            if (CZ[i]) jz += R(CZ[i]) * x[i];
+        }
+        rho = OFF ? R(RHO0) + m0 : m0;
+        ux = (jx + R(0.5) * Fx) / rho;
+        uy = (jy + R(0.5) * Fy) / rho;
+        uz = (jz + R(0.5) * Fz) / rho;
+        bad = !isfinite(rho);
+        if (klass == K_IOLET) {
+            R *up = (R *)((t & 1) ? a.up1 : a.up0);
+            const int64_t vi = s - a.IO0;
+            up[vi] = ux;
+            up[a.Nio + vi] = uy;
+            up[2 * a.Nio + vi] = uz;
+        }
+    }
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) a.ctrl->nan_flag = 1;
+    if (klass == K_IOLET) {
+        const IoletDev &io = a.io[e.tag >> 2];
+        double un = 0.0, rh = 0.0;
+        if (act) {
+            un = (double)ux * io.nrm[0] + (double)uy * io.nrm[1] + (double)uz * io.nrm[2];
+            rh = (double)rho;
+        }
+        const double su = block_sum(un, lds);
+        const double sr = block_sum(rh, lds);
+        if (threadIdx.x == 0) {
+            a.partials[2 * eidx] = su;
+            a.partials[2 * eidx + 1] = sr;
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void body_force(const SegDev &sg, int64_t t, R &Fx, R &Fy, R &Fz) {
+    Fx = Fy = Fz = 0;
+    if (sg.has_force) {
+        const double c = cos(sg.omega * (double)t);
+        Fx = (R)(sg.F0[0] * c);
+        Fy = (R)(sg.F0[1] * c);
+        Fz = (R)(sg.F0[2] * c);
+    }
+}
+
+// One in-place sweep t -> t+1 (MODE: M_BULK, M_BND or M_FUSED).
+template <typename T, int MODE, int ODD>
+__device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    __shared__ double lds[8];
+    const int64_t t = a.ctrl->t;
+    const int direct = a.ctrl->direct;
+    const int eidx = a.e_off + block_index(a.xcd_remap);
+    const Entry e = a.entries[eidx];
+    const int klass = e.tag & 3;
+    const SegDev &sg = a.seg[e.seg];
+    const bool act = (int)threadIdx.x < e.count;
+    const int64_t s = (int64_t)e.start + threadIdx.x;
+    const int64_t N = a.N;
+    T *__restrict__ A = (T *)a.lat0;
+    R x[Q], qv[Q];
+    int32_t sr[Q];
+    const bool bnd = (MODE == M_BND) || (MODE == M_FUSED && klass != K_BULK);
+    if (act) {
+        if (MODE == M_BULK || (MODE == M_FUSED && !bnd))
+            aa_read<T, false, ODD>(a, e, sg, t, s, direct, x, sr, qv);
+        else
+            aa_read<T, true, ODD>(a, e, sg, t, s, direct, x, sr, qv);
+    }
+    R Fx, Fy, Fz;
+    body_force(sg, t, Fx, Fy, Fz);
+    aa_moments<T>(a, e, eidx, t, s, act, x, Fx, Fy, Fz, lds);
+    if (!act) return;
+    R(&f)[Q] = x;
+    collide_site<R, OFF>(f, sg, Fx, Fy, Fz);
+    const bool bz = bnd && sg.wall_mode == WALL_BOUZIDI;
+    if (!ODD) {
+        // swapped stores; slot m receives f*_opp(m), or the final wall value
+        // of the pulled direction m when x_s - c_m is a Bouzidi wall (q >= 1/2)
+#pragma unroll
+        for (int m = 0; m < Q; ++m) {
+            const int mb = opp(m);
+            R v = f[mb];
+            if (bz && m > 0 && sr[m] == -1 && qv[m] >= R(0.5))
+                v = f[mb] / (R(2) * qv[m]) + (R(1) - R(1) / (R(2) * qv[m])) * f[m];
+            stc(A + (size_t)m * N + s, v);
+        }
+    } else {
+        stc(A + s, f[0]);
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            const int kb = opp(k);
+            const int32_t dst = sr[kb];  // the site at x_s + c_k
+            if (dst >= 0) {
+                stc(A + (size_t)k * N + dst, f[k]);
+            } else {
+                R v = f[k];
+                if (bz && dst == -1 && qv[kb] >= R(0.5))
+                    v = f[k] / (R(2) * qv[kb]) + (R(1) - R(1) / (R(2) * qv[kb])) * f[kb];
+                stc(A + (size_t)kb * N + s, v);
+            }
+        }
+    }
+}
+
+template <typename T, int MODE, int ODD>
+__global__ void __launch_bounds__(256) k_aa(KArgs a) {
+    aa_sweep_body<T, MODE, ODD>(a);
+}
+
+// Moments-only pass over f(t) (iolet means and history at step t).
+template <typename T, int ODD>
+__global__ void __launch_bounds__(256) k_aa_moments(KArgs a) {
+    using R = typename Arith<T>::R;
+    __shared__ double lds[8];
+    const int64_t t = a.ctrl->t;
+    const int direct = a.ctrl->direct;
+    const int eidx = blockIdx.x;
+    const Entry e = a.entries[eidx];
+    const SegDev &sg = a.seg[e.seg];
+    const bool act = (int)threadIdx.x < e.count;
+    const int64_t s = (int64_t)e.start + threadIdx.x;
+    R x[Q], qv[Q];
+    int32_t sr[Q];
+    if (act) aa_read<T, true, ODD>(a, e, sg, t, s, direct, x, sr, qv);
+    R Fx, Fy, Fz;
+    body_force(sg, t, Fx, Fy, Fz);
+    aa_moments<T>(a, e, eidx, t, s, act, x, Fx, Fy, Fz, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Observables of f(t): density, velocity, wall shear stress (FP64), and
 // optionally the full populations.  f(t) is re-streamed from f*(t-1) with
@@ -374,7 +801,14 @@ __global__ void __launch_bounds__(256) k_observe(KArgs a) {
     const int64_t s = (int64_t)e.start + threadIdx.x;
     const int64_t N = a.N;
     R x[Q];
-    if (direct) {
+    if (a.aa) {
+        R qv[Q];
+        int32_t sr[Q];
+        if (t & 1)
+            aa_read<T, true, 1>(a, e, sg, t, s, direct, x, sr, qv);
+        else
+            aa_read<T, true, 0>(a, e, sg, t, s, direct, x, sr, qv);
+    } else if (direct) {
         const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
 #pragma unroll
         for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s);
@@ -441,7 +875,7 @@ __global__ void k_load_raw(KArgs a) {
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     const int64_t t = a.ctrl->t;
-    T *raw = (T *)(((t + 1) & 1) ? a.lat1 : a.lat0);
+    T *raw = (T *)((!a.aa && ((t + 1) & 1)) ? a.lat1 : a.lat0);
     const int64_t total = (int64_t)Q * a.N;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -457,7 +891,7 @@ __global__ void k_fill_rest(KArgs a) {
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     const int64_t t = a.ctrl->t;
-    T *raw = (T *)(((t + 1) & 1) ? a.lat1 : a.lat0);
+    T *raw = (T *)((!a.aa && ((t + 1) & 1)) ? a.lat1 : a.lat0);
     const int64_t total = (int64_t)Q * a.N;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
@@ -473,21 +907,52 @@ __global__ void k_gather_obs(const double *__restrict__ src, const int64_t *__re
         out[k] = src[c2g[k]];
 }
 
+// Full f(t) (double, internal order) -> the in-place lattice at an odd step,
+// in the arrangement the odd sweep gathers from: f_j(x) at
+// A[opp(j)][x - c_j] when that site is fluid, else at A[j][x].
+template <typename T>
+__global__ void __launch_bounds__(256) k_aa_load_odd(KArgs a) {
+    using R = typename Arith<T>::R;
+    constexpr bool OFF = Arith<T>::OFF;
+    const Entry e = a.entries[blockIdx.x];
+    if ((int)threadIdx.x >= e.count) return;
+    const int64_t s = (int64_t)e.start + threadIdx.x;
+    const int64_t N = a.N;
+    T *A = (T *)a.lat0;
+    stc(A + s, (R)(a.fin[s] - (OFF ? wgt<double>(0) * RHO0 : 0.0)));
+#pragma unroll
+    for (int j = 1; j < Q; ++j) {
+        const R v = (R)(a.fin[(size_t)j * N + s] - (OFF ? wgt<double>(j) * RHO0 : 0.0));
+        const int32_t up = a.src[(size_t)(j - 1) * N + s];
+        if (up >= 0)
+            stc(A + (size_t)opp(j) * N + up, v);
+        else
+            stc(A + (size_t)j * N + s, v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// part: 0 = every launch of the step, 1 = the bulk-site kernel, 2 = the
+// boundary-site (or fused) kernel, 3 = the finalize kernel.
 template <typename T>
-static int step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStream_t st, int part) {
+static int step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStream_t st, int part, bool fused) {
     KArgs a = a0;
-    if (n_bulk > 0 && part != 2) {
+    if (fused) {
         a.e_off = 0;
-        hipLaunchKernelGGL((k_step<T, M_BULK>), dim3(n_bulk), dim3(block), 0, st, a);
+        if ((part == 0 || part == 2) && n_bnd > 0) launch_mode<T, M_FUSED>(n_bnd, block, st, a);
+    } else {
+        if (n_bulk > 0 && (part == 0 || part == 1)) {
+            a.e_off = 0;
+            launch_mode<T, M_BULK>(n_bulk, block, st, a);
+        }
+        if (n_bnd > 0 && (part == 0 || part == 2)) {
+            a.e_off = n_bulk;
+            launch_mode<T, M_BND>(n_bnd, block, st, a);
+        }
     }
-    if (n_bnd > 0 && part != 1) {
-        a.e_off = n_bulk;
-        hipLaunchKernelGGL((k_step<T, M_BND>), dim3(n_bnd), dim3(block), 0, st, a);
-    }
-    if (part != 1) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, 0);
+    if (part == 0 || part == 3) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_STEP);
     return (int)hipGetLastError();
 }
 
@@ -497,7 +962,7 @@ static int init_t(const KArgs &a0, int n_entries, int block, hipStream_t st) {
     a.e_off = 0;
     a.xcd_remap = 0;
     hipLaunchKernelGGL((k_step<T, M_RAW>), dim3(n_entries), dim3(block), 0, st, a);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, 1);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_RAW);
     return (int)hipGetLastError();
 }
 
@@ -508,11 +973,11 @@ static int grid_for(int64_t total) {
     return (int)g;
 }
 
-int launch_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part) {
+int launch_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part, bool fused) {
     hipStream_t st = (hipStream_t)stream;
-    if (prec == PREC_F64) return step_t<double>(a, n_bulk, n_bnd, block, st, part);
-    if (prec == PREC_F32) return step_t<float>(a, n_bulk, n_bnd, block, st, part);
-    return step_t<__half>(a, n_bulk, n_bnd, block, st, part);
+    if (prec == PREC_F64) return step_t<double>(a, n_bulk, n_bnd, block, st, part, fused);
+    if (prec == PREC_F32) return step_t<float>(a, n_bulk, n_bnd, block, st, part, fused);
+    return step_t<__half>(a, n_bulk, n_bnd, block, st, part, fused);
 }
 
 int launch_init(int prec, const KArgs &a, int n_entries, int block, void *stream) {
@@ -542,6 +1007,71 @@ int launch_load_raw(int prec, const KArgs &a, void *stream) {
         hipLaunchKernelGGL(k_load_raw<float>, dim3(g), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_load_raw<__half>, dim3(g), dim3(256), 0, st, a);
+    return (int)hipGetLastError();
+}
+
+template <typename T, int ODD>
+static int aa_step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStream_t st, int part, bool fused) {
+    KArgs a = a0;
+    if (fused) {
+        a.e_off = 0;
+        if ((part == 0 || part == 2) && n_bnd > 0)
+            hipLaunchKernelGGL((k_aa<T, M_FUSED, ODD>), dim3(n_bnd), dim3(block), 0, st, a);
+    } else {
+        if (n_bulk > 0 && (part == 0 || part == 1)) {
+            a.e_off = 0;
+            hipLaunchKernelGGL((k_aa<T, M_BULK, ODD>), dim3(n_bulk), dim3(block), 0, st, a);
+        }
+        if (n_bnd > 0 && (part == 0 || part == 2)) {
+            a.e_off = n_bulk;
+            hipLaunchKernelGGL((k_aa<T, M_BND, ODD>), dim3(n_bnd), dim3(block), 0, st, a);
+        }
+    }
+    if (part == 0 || part == 3) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_AA_SWEEP);
+    return (int)hipGetLastError();
+}
+
+int launch_aa_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part, bool fused,
+                   int odd) {
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == PREC_F64)
+        return odd ? aa_step_t<double, 1>(a, n_bulk, n_bnd, block, st, part, fused)
+                   : aa_step_t<double, 0>(a, n_bulk, n_bnd, block, st, part, fused);
+    if (prec == PREC_F32)
+        return odd ? aa_step_t<float, 1>(a, n_bulk, n_bnd, block, st, part, fused)
+                   : aa_step_t<float, 0>(a, n_bulk, n_bnd, block, st, part, fused);
+    return odd ? aa_step_t<__half, 1>(a, n_bulk, n_bnd, block, st, part, fused)
+               : aa_step_t<__half, 0>(a, n_bulk, n_bnd, block, st, part, fused);
+}
+
+template <typename T>
+static void aa_moments_t(const KArgs &a, int n_entries, int block, hipStream_t st, int odd) {
+    if (odd)
+        hipLaunchKernelGGL((k_aa_moments<T, 1>), dim3(n_entries), dim3(block), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_aa_moments<T, 0>), dim3(n_entries), dim3(block), 0, st, a);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_AA_MOMENTS);
+}
+
+int launch_aa_moments(int prec, const KArgs &a, int n_entries, int block, void *stream, int odd) {
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == PREC_F64)
+        aa_moments_t<double>(a, n_entries, block, st, odd);
+    else if (prec == PREC_F32)
+        aa_moments_t<float>(a, n_entries, block, st, odd);
+    else
+        aa_moments_t<__half>(a, n_entries, block, st, odd);
+    return (int)hipGetLastError();
+}
+
+int launch_aa_load_odd(int prec, const KArgs &a, int n_entries, int block, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == PREC_F64)
+        hipLaunchKernelGGL(k_aa_load_odd<double>, dim3(n_entries), dim3(block), 0, st, a);
+    else if (prec == PREC_F32)
+        hipLaunchKernelGGL(k_aa_load_odd<float>, dim3(n_entries), dim3(block), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_aa_load_odd<__half>, dim3(n_entries), dim3(block), 0, st, a);
     return (int)hipGetLastError();
 }
 

@@ -40,6 +40,12 @@ class Scenario:
     mode: int = 0
 
 
+def from_workload(wl):
+    """Scenario from a synth.workloads.Workload."""
+    doms = [Dom(d.geo, d.tau, d.bouzidi, tuple(d.F0), d.omega, dict(d.inlets), dict(d.outlets)) for d in wl.domains]
+    return Scenario(doms, list(wl.pairs), wl.mode)
+
+
 def build_oracle(sc, oracle):
     s = oracle.System(len(sc.doms))
     for d, dm in enumerate(sc.doms):
@@ -61,8 +67,8 @@ def build_oracle(sc, oracle):
     return s
 
 
-def build_gpu(sc, hl, precision="f64"):
-    ctx = hl.Context(0, precision)
+def build_gpu(sc, hl, precision="f64", order=0):
+    ctx = hl.Context(0, precision, order=order)
     for d, dm in enumerate(sc.doms):
         ctx.add_domain()
         ctx.load_geometry(d, dm.geo)

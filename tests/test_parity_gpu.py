@@ -199,7 +199,7 @@ def test_nan_is_reported_as_divergence(hl):
     assert ei.value.code == hl.HL_E_DIVERGED
 
 
-@pytest.mark.parametrize("block,flags", [(64, 0), (128, 1), (256, 1)])
+@pytest.mark.parametrize("block,flags", [(64, 0), (128, 1), (256, 1), (64, 4), (256, 4)])
 def test_schedules_agree(hl, oracle_mod, block, flags):
     sc = c1_scenario(nz=24)
     o = build_oracle(sc, oracle_mod)
@@ -289,8 +289,9 @@ def test_autotune_keeps_state(hl):
     assert blk in (64, 128, 256)
 
 
-@pytest.mark.parametrize("order", [1, 2, 3, 4, 6])
-def test_site_orders_agree_with_oracle(hl, oracle_mod, order):
+@pytest.mark.parametrize("order,sched", [(1, 0), (2, 0), (3, 0), (4, 0), (6, 0), (8, 0), (8, 2), (8, 3), (2, 2), (0, 3),
+                                         (2, 4), (2, 5), (8, 4), (0, 4)])
+def test_site_orders_agree_with_oracle(hl, oracle_mod, order, sched):
     """Every internal site layout gives the oracle's result: Morton order of
     bulk and/or boundary sites, wall sites interleaved with bulk sites."""
     geo = synth.tree_geometry(3, 7.0, 20100416, lam=6.0)
@@ -303,6 +304,140 @@ def test_site_orders_agree_with_oracle(hl, oracle_mod, order):
     g.set_tau(0, 0.6)
     g.set_wall_mode(0, hl.HL_WALL_BOUZIDI)
     g.set_inlet_velocity(0, 0, 0.01)
+    g.set_schedule(128, sched)
     o.step(150)
     g.step(150)
     check64(errors(g, o))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_pair_kernel_is_bitwise_equal_to_single(hl, prec):
+    """The two-sites-per-lane bulk kernel performs the same arithmetic as the
+    one-site kernel, so the offset-storage states agree bit for bit."""
+    res = []
+    for flags in (0, hl.HL_SCHED_PAIRS):
+        geo = synth.tree_geometry(3, 7.0, 20100416, lam=6.0)
+        g = hl.Context(0, prec, order=2)
+        g.add_domain()
+        g.load_geometry(0, geo)
+        g.set_tau(0, 0.6)
+        g.set_wall_mode(0, hl.HL_WALL_BOUZIDI)
+        g.set_inlet_velocity(0, 0, 0.01)
+        g.set_schedule(256, flags)
+        g.step(60)
+        res.append(g.populations(0))
+    assert np.array_equal(res[0], res[1])
+
+
+# ---------------------------------------------------------------------------
+# In-place (AA-pattern) scheme: the same oracle agreement as the two-lattice
+# scheme, for every boundary kind, both sweep parities and both layouts.
+# ---------------------------------------------------------------------------
+AA = 16
+
+
+@pytest.mark.parametrize("order,sched", [(AA, 0), (AA | 2, 0), (AA | 8, 2), (AA | 8, 3), (AA, 1)])
+def test_aa_tree_bouzidi(hl, oracle_mod, order, sched):
+    geo = synth.tree_geometry(3, 7.0, 20100416, lam=6.0)
+    outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}
+    sc = Scenario([Dom(geo, tau=0.6, bouzidi=True, inlets={0: (0.01, (), (), 1.0)}, outlets=outs)])
+    o = build_oracle(sc, oracle_mod)
+    g = build_gpu(sc, hl, "f64", order=order)
+    g.set_schedule(128, sched)
+    o.step(151)
+    g.step(151)
+    check64(errors(g, o))
+    np.testing.assert_allclose(g.iolet_bc(0, which=1), o.last_bc(0), rtol=1e-12, atol=1e-15)
+
+
+def test_aa_cylinder_sbb_1000_steps(hl, oracle_mod):
+    g, o = run_both_order(c1_scenario(), hl, oracle_mod, 1000, AA)
+    check64(errors(g, o))
+
+
+def test_aa_cylinder_exact_q_bouzidi(hl, oracle_mod):
+    g, o = run_both_order(c1_scenario(q="cylinder", bouzidi=True), hl, oracle_mod, 333, AA)
+    check64(errors(g, o))
+
+
+def test_aa_pulsatile_series_force(hl, oracle_mod):
+    geo = synth.tubes(2, radius=4.0, length=20)
+    sc = Scenario([Dom(geo, tau=0.7, F0=(0.0, 1e-6, 2e-6), omega=0.05,
+                       inlets={0: (0.008, (0.002, -0.001, 0.0005), (0.001, 0.0, -0.0007), 60.0),
+                               1: (0.004, (0.001,), (0.0,), 45.0)},
+                       outlets={2: (1.0, (0.0005,), (0.0002,), 80.0), 3: (1.001, (), (), 1.0)})])
+    g, o = run_both_order(sc, hl, oracle_mod, 251, AA)
+    check64(errors(g, o))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_aa_coupled_1to3(hl, oracle_mod, mode):
+    art = synth.tubes(1, radius=4.0, length=24)
+    ven = synth.tubes(3, radius=4.0, length=24)
+    dp = [0.30, 0.52, 0.69]
+    s = oracle_mod.velocity_factors(dp, [1.0, 0.6156, 0.5639], [1, 1, 1], 1.0)
+    sc = Scenario([Dom(art, tau=0.8, bouzidi=True, inlets={0: (0.01, (), (), 1.0)}),
+                   Dom(ven, tau=0.8)],
+                  pairs=[(0, 1, 1, i, float(s[i]), dp[i]) for i in range(3)], mode=mode)
+    g, o = run_both_order(sc, hl, oracle_mod, 601, AA)
+    for d in (0, 1):
+        check64(errors(g, o, d))
+        np.testing.assert_allclose(g.iolet_bc(d, which=1), o.last_bc(d), rtol=1e-12, atol=1e-15)
+    nxt = [g.iolet_bc(d, which=0) for d in (0, 1)]
+    o.step(1)                     # the oracle's values for step 601 are those its next step uses
+    for d in (0, 1):
+        np.testing.assert_allclose(nxt[d], o.last_bc(d), rtol=1e-12, atol=1e-15)
+
+
+def run_both_order(sc, hl, oracle_mod, steps, order):
+    o = build_oracle(sc, oracle_mod)
+    g = build_gpu(sc, hl, "f64", order=order)
+    o.step(steps)
+    g.step(steps)
+    g.sync()
+    return g, o
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_aa_checkpoint_graph_and_reload(hl, prec):
+    """In-place scheme: graph replay equals plain launches bit for bit from an
+    odd start, checkpoints resume bit for bit, and reloading the populations
+    at an odd step continues exactly (FP64: bitwise)."""
+    ref = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+    ref.set_drive(hl.HL_DRIVE_LAUNCH)
+    ref.step(3)
+    ref.step(40)
+    fa = ref.populations(0)
+    g = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+    g.set_drive(hl.HL_DRIVE_GRAPH, 8)
+    g.step(3)
+    g.step(40)
+    assert np.array_equal(g.populations(0), fa)
+    b = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+    b.step(21)
+    blob = b.get_state()
+    c = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+    c.commit()
+    c.set_state(blob)
+    c.step(22)
+    assert np.array_equal(c.populations(0), fa)
+    if prec == "f64":
+        d = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+        d.step(21)
+        f21 = d.populations(0)
+        d.set_populations(0, f21)
+        assert np.array_equal(d.populations(0), f21)
+        d.step(22)
+        assert np.abs(d.populations(0) - fa).max() < 1e-15
+
+
+def test_aa_offset_storage_errors(hl, oracle_mod):
+    for prec, bound in (("f32", 2e-4), ("f16", 0.05)):
+        sc = c1_scenario()
+        o = build_oracle(sc, oracle_mod)
+        g = build_gpu(sc, hl, prec, order=AA)
+        o.step(1000)
+        g.step(1000)
+        err = errors(g, o)
+        print("AA", prec, err, flush=True)
+        assert err["e_u"] < bound
