@@ -217,6 +217,78 @@ def traffic_from_profile(prec, layout, sched):
     return e.get("bytes_per_launch")
 
 
+def run_multi(hl, torch, args):
+    """Multi-domain workloads (one context, every domain in the same launches):
+    the coupled arterial-venous pair or the ensemble of uneven trees."""
+    import synth
+    t0 = time.perf_counter()
+    if args.workload == "coupled":
+        wl = synth.workloads.coupled_pair(lam=args.lam)
+    else:
+        wl = synth.workloads.ensemble()
+    n = sum(d.geo.n for d in wl.domains)
+    log(f"{wl.name}: {len(wl.domains)} domains, {n} sites, {len(wl.pairs)} coupled pairs "
+        f"({time.perf_counter() - t0:.1f} s)")
+    layouts = [int(v) for v in args.layouts.split(",") if v.strip()]
+    out = {}
+    for prec in [p.strip() for p in args.precisions.split(",") if p.strip()]:
+        best = None
+        for order in layouts:
+            ctx = hl.Context(0, prec, order=order)
+            for d, dm in enumerate(wl.domains):
+                ctx.add_domain()
+                ctx.load_geometry(d, dm.geo)
+                ctx.set_tau(d, dm.tau)
+                ctx.set_wall_mode(d, hl.HL_WALL_BOUZIDI if dm.bouzidi else hl.HL_WALL_SBB)
+                for k, (a0, a, b, T) in dm.inlets.items():
+                    ctx.set_inlet_velocity(d, k, a0, a, b, T)
+                for k, (r0, a, b, T) in dm.outlets.items():
+                    ctx.set_outlet_density(d, k, r0, a, b, T)
+            for pr in wl.pairs:
+                ctx.couple(*pr)
+            ctx.set_stream(torch.cuda.current_stream())
+            ctx.commit()
+            if args.autotune_ms > 0:
+                ctx.autotune(args.autotune_ms)
+            ctx.step(4)
+            ms, _ = measure(ctx, torch, args.probe_steps)
+            log(f"{prec} layout {order}: schedule {ctx.schedule()}, {n * args.probe_steps / (ms * 1e-3) / 1e6:.0f} MLUPS")
+            if best is None or ms < best[0]:
+                if best is not None:
+                    best[2].close()
+                best = (ms, order, ctx)
+            else:
+                ctx.close()
+        _, order, ctx = best
+        ctx.step(args.warmup)
+        ms, wall = measure(ctx, torch, args.steps)
+        mlups = n * args.steps / (ms * 1e-3) / 1e6
+        info = ctx.info()
+        aa = bool(order & hl.HL_SCHEME_AA)
+        out[prec] = {"mlups": round(mlups, 1), "ms_per_step": round(ms / args.steps, 5), "layout_flags": order,
+                     "schedule": list(ctx.schedule()), "alg_GBps": round(mlups * 1e6 * bytes_per_site(prec, aa) / 1e9, 1),
+                     "device_GB": round(info["device_bytes"] / 1e9, 2), "t": ctx.t}
+        if wl.pairs:
+            mu, _ = ctx.iolet_stats(0)
+            mv, _ = ctx.iolet_stats(1)
+            out[prec]["mean_u_arterial_root"] = float(mu[0])
+            out[prec]["mean_u_venous_root"] = float(mv[0])
+        log(prec, json.dumps(out[prec]))
+        ctx.close()
+    head = "f32" if "f32" in out else next(iter(out))
+    line = {
+        "metric": "MLUPS + achieved HBM GB/s (% peak), FP64 vs FP32 at stated error, 1 GPU",
+        "value": out[head]["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": out[head]["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": head, "data": "synthetic",
+        "config": {"workload": wl.name, "sites": n, "domains": len(wl.domains), "pairs": len(wl.pairs),
+                   "domain_sites": [d.geo.n for d in wl.domains] if len(wl.domains) <= 64 else None,
+                   "meta": {k: v for k, v in wl.meta.items() if k != "targets"}},
+        "variants": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def copy_calibration(torch):
     """A plain device copy of known size for scaling the HBM byte counters."""
     nbytes = 1 << 30
@@ -245,6 +317,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and full-size parity")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
+    ap.add_argument("--workload", default="artery", choices=["artery", "coupled", "ensemble"],
+                    help="artery: the branching-artery line (default); coupled / ensemble: multi-domain workloads")
+    ap.add_argument("--lam", type=float, default=8.0, help="segment length / radius of the coupled trees")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -261,6 +336,9 @@ def main():
     import paper_2010_04144_amd as hl
     import synth
 
+    if args.workload != "artery":
+        run_multi(hl, torch, args)
+        return
     t0 = time.perf_counter()
     geo = synth.murray_tree_c2(box=args.box)
     log(f"geometry: {geo.n} sites, fill {geo.meta['fill']:.4f}, lambda {geo.meta['lam']:.3f}, "

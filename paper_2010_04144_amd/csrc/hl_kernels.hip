@@ -41,16 +41,34 @@ __device__ __forceinline__ constexpr R wgt(int i) {
     return i == 0 ? R(1.0) / R(3.0) : (i <= 6 ? R(1.0) / R(18.0) : R(1.0) / R(36.0));
 }
 
+// a / b in the arithmetic type: IEEE division in FP64 (the operation of the
+// FP64 reference form); in FP32 a times the hardware reciprocal of b (1 ulp;
+// the divisors here, a density near rho0 and 2q in [1, 2], are far from the
+// denormal range), which the compiler shares between quotients with the
+// same divisor.
+__device__ __forceinline__ double over(double a, double b) { return a / b; }
+__device__ __forceinline__ float over(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // Storage type -> arithmetic type.  FP64 stores f, FP32/FP16 store offsets.
 template <typename T> struct Arith { using R = float; static constexpr bool OFF = true; };
 template <> struct Arith<double> { using R = double; static constexpr bool OFF = false; };
 
-__device__ __forceinline__ double ldc(const double *p) { return *p; }
-__device__ __forceinline__ float ldc(const float *p) { return *p; }
-__device__ __forceinline__ float ldc(const __half *p) { return __half2float(*p); }
-__device__ __forceinline__ void stc(double *p, double v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ void stc(float *p, float v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ void stc(__half *p, float v) { *p = __float2half_rn(v); }
+// Population storage.  ld/st take the lattice row (direction slot) so that
+// the weight-normalised FP16 form can scale by w_row (w_i = w_opp(i), so the
+// row alone fixes the weight in both the natural and the swapped layout).
+struct h16w {
+    __half v;
+};
+__device__ __forceinline__ double ldc(const double *p, int) { return *p; }
+__device__ __forceinline__ float ldc(const float *p, int) { return *p; }
+__device__ __forceinline__ float ldc(const __half *p, int) { return __half2float(*p); }
+__device__ __forceinline__ float ldc(const h16w *p, int row) { return __half2float(p->v) * wgt<float>(row); }
+__device__ __forceinline__ void stc(double *p, double v, int) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void stc(float *p, float v, int) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void stc(__half *p, float v, int) { *p = __float2half_rn(v); }
+__device__ __forceinline__ void stc(h16w *p, float v, int row) {
+    p->v = __float2half_rn(v * (row == 0 ? 3.0f : (row <= 6 ? 18.0f : 36.0f)));
+}
 
 template <typename T>
 __device__ __forceinline__ const T *lat_ptr(const KArgs &a, int64_t parity) {
@@ -82,13 +100,13 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
     int32_t sr[Q];
 #pragma unroll
     for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
-    x[0] = ldc(lin + s);
+    x[0] = ldc(lin + s, 0);
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
         if (BND)
-            x[j] = (sr[j] >= 0) ? ldc(lin + (size_t)j * N + sr[j]) : R(0);
+            x[j] = (sr[j] >= 0) ? ldc(lin + (size_t)j * N + sr[j], j) : R(0);
         else
-            x[j] = ldc(lin + (size_t)j * N + sr[j]);
+            x[j] = ldc(lin + (size_t)j * N + sr[j], j);
     }
     if (!BND) return;
 
@@ -131,7 +149,7 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
         // f*_i(s) feeds direction ib (bounce-back, Bouzidi, inlet) and, for a
         // Bouzidi wall link, direction i itself (q >= 1/2)
         const bool need = (sr[ib] == -1) || (sr[ib] <= -2 && !outlet) || (bz && sr[i] == -1);
-        own[i] = need ? ldc(lin + (size_t)i * N + s) : R(0);
+        own[i] = need ? ldc(lin + (size_t)i * N + s, i) : R(0);
         qv[i] = (bz && sr[i] == -1) ? (R)a.bq[(size_t)(i - 1) * a.Nb + b] : R(0.5);
     }
     // Phase 2: the boundary rules, from registers only.
@@ -147,7 +165,7 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
                     // second node x_s - c_jb = x_s + c_j, pulled as x[jb]
                     x[j] = (sr[jb] >= 0) ? R(2) * q * own[jb] + (R(1) - R(2) * q) * x[jb] : own[jb];
                 } else {
-                    x[j] = own[jb] / (R(2) * q) + (R(1) - R(1) / (R(2) * q)) * own[j];
+                    x[j] = over(own[jb], R(2) * q) + (R(1) - over(R(1), R(2) * q)) * own[j];
                 }
             } else {
                 x[j] = own[jb];
@@ -281,9 +299,9 @@ __device__ __forceinline__ bool collide_site(R (&x)[Q], const SegDev &sg, R Fx, 
     } else {
         rho = m0;
     }
-    const R ux = (jx + R(0.5) * Fx) / rho;
-    const R uy = (jy + R(0.5) * Fy) / rho;
-    const R uz = (jz + R(0.5) * Fz) / rho;
+    const R ux = over(jx + R(0.5) * Fx, rho);
+    const R uy = over(jy + R(0.5) * Fy, rho);
+    const R uz = over(jz + R(0.5) * Fz, rho);
     const R it = (R)sg.inv_tau;
     const R uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
@@ -331,7 +349,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
         if (MODE == M_RAW) {
             const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s);
+            for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s, i);
         } else if (MODE == M_FUSED) {
             if (klass == K_BULK)
                 gather<T, false>(a, e, sg, t, s, x);
@@ -367,9 +385,9 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
         } else {
             rho = m0;
         }
-        ux = (jx + R(0.5) * Fx) / rho;
-        uy = (jy + R(0.5) * Fy) / rho;
-        uz = (jz + R(0.5) * Fz) / rho;
+        ux = over(jx + R(0.5) * Fx, rho);
+        uy = over(jy + R(0.5) * Fy, rho);
+        uz = over(jz + R(0.5) * Fz, rho);
         bad = !isfinite(rho);
 
         if (klass == K_IOLET) {
@@ -396,7 +414,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
                              (R(3) * (R(CZ[i]) - uz) + R(9) * cu * R(CZ[i])) * Fz;
                 o += (R)sg.guo_pref * wgt<R>(i) * sF;
             }
-            stc(lout + (size_t)i * N + s, o);
+            stc(lout + (size_t)i * N + s, o, i);
         }
     }
     if (__ballot(bad) != 0 && (tid & 63) == 0) a.ctrl->nan_flag = 1;
@@ -464,7 +482,7 @@ __global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
         x0[0] = cvt(v.x);
         x1[0] = cvt(v.y);
     } else {
-        x0[0] = ldc(lin + s);
+        x0[0] = ldc(lin + s, 0);
         x1[0] = R(0);
     }
 #pragma unroll
@@ -479,11 +497,11 @@ __global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
                 x0[j] = cvt(v.x);
                 x1[j] = cvt(v.y);
             } else {
-                x0[j] = ldc(row + sv.x);
-                x1[j] = ldc(row + sv.y);
+                x0[j] = ldc(row + sv.x, j);
+                x1[j] = ldc(row + sv.y, j);
             }
         } else {
-            x0[j] = ldc(row + sp[0]);
+            x0[j] = ldc(row + sp[0], j);
             x1[j] = R(0);
         }
     }
@@ -506,7 +524,7 @@ __global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
             v.y = (E)x1[i];
             __builtin_nontemporal_store(v, (V2 *)p);
         } else {
-            stc(p, x0[i]);
+            stc(p, x0[i], i);
         }
     }
 }
@@ -521,7 +539,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
 
 template <typename T, int MODE>
 static void launch_mode(int grid, int block, hipStream_t st, const KArgs &a) {
-    if constexpr (MODE == M_BULK) {
+    if constexpr (MODE == M_BULK && !std::is_same<T, h16w>::value) {
         if (a.n_pairs_blocks > 0) {
             hipLaunchKernelGGL((k_bulk2<T>), dim3(a.n_pairs_blocks), dim3(block), 0, st, a);
             return;
@@ -566,18 +584,18 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
     }
     if (!ODD) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) x[i] = ldc(A + (size_t)i * N + s);
+        for (int i = 0; i < Q; ++i) x[i] = ldc(A + (size_t)i * N + s, i);
     } else {
         // (after a reload at an odd step the lattice holds f(t) in the same
         // arrangement, so the same gather reads it back)
-        x[0] = ldc(A + s);
+        x[0] = ldc(A + s, 0);
 #pragma unroll
         for (int j = 1; j < Q; ++j) {
             const int jb = opp(j);
             if (BND)
-                x[j] = (sr[j] >= 0) ? ldc(A + (size_t)jb * N + sr[j]) : ldc(A + (size_t)j * N + s);
+                x[j] = (sr[j] >= 0) ? ldc(A + (size_t)jb * N + sr[j], jb) : ldc(A + (size_t)j * N + s, j);
             else
-                x[j] = ldc(A + (size_t)jb * N + sr[j]);
+                x[j] = ldc(A + (size_t)jb * N + sr[j], jb);
         }
     }
     if (!BND) return;
@@ -658,9 +676,9 @@ __device__ __forceinline__ void aa_moments(const KArgs &a, const Entry &e, int e
             if (CZ[i]) jz += R(CZ[i]) * x[i];
         }
         rho = OFF ? R(RHO0) + m0 : m0;
-        ux = (jx + R(0.5) * Fx) / rho;
-        uy = (jy + R(0.5) * Fy) / rho;
-        uz = (jz + R(0.5) * Fz) / rho;
+        ux = over(jx + R(0.5) * Fx, rho);
+        uy = over(jy + R(0.5) * Fy, rho);
+        uz = over(jz + R(0.5) * Fz, rho);
         bad = !isfinite(rho);
         if (klass == K_IOLET) {
             R *up = (R *)((t & 1) ? a.up1 : a.up0);
@@ -738,22 +756,22 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
             const int mb = opp(m);
             R v = f[mb];
             if (bz && m > 0 && sr[m] == -1 && qv[m] >= R(0.5))
-                v = f[mb] / (R(2) * qv[m]) + (R(1) - R(1) / (R(2) * qv[m])) * f[m];
-            stc(A + (size_t)m * N + s, v);
+                v = over(f[mb], R(2) * qv[m]) + (R(1) - over(R(1), R(2) * qv[m])) * f[m];
+            stc(A + (size_t)m * N + s, v, m);
         }
     } else {
-        stc(A + s, f[0]);
+        stc(A + s, f[0], 0);
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int kb = opp(k);
             const int32_t dst = sr[kb];  // the site at x_s + c_k
             if (dst >= 0) {
-                stc(A + (size_t)k * N + dst, f[k]);
+                stc(A + (size_t)k * N + dst, f[k], k);
             } else {
                 R v = f[k];
                 if (bz && dst == -1 && qv[kb] >= R(0.5))
-                    v = f[k] / (R(2) * qv[kb]) + (R(1) - R(1) / (R(2) * qv[kb])) * f[kb];
-                stc(A + (size_t)kb * N + s, v);
+                    v = over(f[k], R(2) * qv[kb]) + (R(1) - over(R(1), R(2) * qv[kb])) * f[kb];
+                stc(A + (size_t)kb * N + s, v, kb);
             }
         }
     }
@@ -762,6 +780,21 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
 template <typename T, int MODE, int ODD>
 __global__ void __launch_bounds__(256) k_aa(KArgs a) {
     aa_sweep_body<T, MODE, ODD>(a);
+}
+
+// FP32/FP16 boundary and fused sweeps with the register budget of four waves
+// per SIMD (their odd form would otherwise run three).
+template <typename T, int MODE, int ODD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_aa_occ(KArgs a) {
+    aa_sweep_body<T, MODE, ODD>(a);
+}
+
+template <typename T, int MODE, int ODD>
+static void launch_aa_mode(int grid, int block, hipStream_t st, const KArgs &a) {
+    if constexpr (std::is_same<T, double>::value || MODE == M_BULK)
+        hipLaunchKernelGGL((k_aa<T, MODE, ODD>), dim3(grid), dim3(block), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_aa_occ<T, MODE, ODD>), dim3(grid), dim3(block), 0, st, a);
 }
 
 // Moments-only pass over f(t) (iolet means and history at step t).
@@ -811,7 +844,7 @@ __global__ void __launch_bounds__(256) k_observe(KArgs a) {
     } else if (direct) {
         const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s);
+        for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s, i);
     } else {
         gather<T, true>(a, e, sg, t - 1, s, x);
     }
@@ -881,7 +914,7 @@ __global__ void k_load_raw(KArgs a) {
          k += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(k / a.N);
         const double v = a.fin[k] - (OFF ? wgt<double>(i) * RHO0 : 0.0);
-        stc(raw + k, (R)v);
+        stc(raw + k, (R)v, i);
     }
 }
 
@@ -896,7 +929,7 @@ __global__ void k_fill_rest(KArgs a) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(k / a.N);
-        stc(raw + k, OFF ? R(0) : (R)(wgt<double>(i) * RHO0));
+        stc(raw + k, OFF ? R(0) : (R)(wgt<double>(i) * RHO0), i);
     }
 }
 
@@ -919,15 +952,15 @@ __global__ void __launch_bounds__(256) k_aa_load_odd(KArgs a) {
     const int64_t s = (int64_t)e.start + threadIdx.x;
     const int64_t N = a.N;
     T *A = (T *)a.lat0;
-    stc(A + s, (R)(a.fin[s] - (OFF ? wgt<double>(0) * RHO0 : 0.0)));
+    stc(A + s, (R)(a.fin[s] - (OFF ? wgt<double>(0) * RHO0 : 0.0)), 0);
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
         const R v = (R)(a.fin[(size_t)j * N + s] - (OFF ? wgt<double>(j) * RHO0 : 0.0));
         const int32_t up = a.src[(size_t)(j - 1) * N + s];
         if (up >= 0)
-            stc(A + (size_t)opp(j) * N + up, v);
+            stc(A + (size_t)opp(j) * N + up, v, opp(j));
         else
-            stc(A + (size_t)j * N + s, v);
+            stc(A + (size_t)j * N + s, v, j);
     }
 }
 
@@ -973,41 +1006,42 @@ static int grid_for(int64_t total) {
     return (int)g;
 }
 
+// Storage-type dispatch: calls f with a value of the storage type of `prec`.
+template <typename F>
+static int by_prec(int prec, F &&f) {
+    switch (prec) {
+    case PREC_F64: return f(double());
+    case PREC_F32: return f(float());
+    case PREC_F16: return f(__half());
+    default: return f(h16w());
+    }
+}
+
 int launch_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part, bool fused) {
     hipStream_t st = (hipStream_t)stream;
-    if (prec == PREC_F64) return step_t<double>(a, n_bulk, n_bnd, block, st, part, fused);
-    if (prec == PREC_F32) return step_t<float>(a, n_bulk, n_bnd, block, st, part, fused);
-    return step_t<__half>(a, n_bulk, n_bnd, block, st, part, fused);
+    return by_prec(prec, [&](auto z) { return step_t<decltype(z)>(a, n_bulk, n_bnd, block, st, part, fused); });
 }
 
 int launch_init(int prec, const KArgs &a, int n_entries, int block, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    if (prec == PREC_F64) return init_t<double>(a, n_entries, block, st);
-    if (prec == PREC_F32) return init_t<float>(a, n_entries, block, st);
-    return init_t<__half>(a, n_entries, block, st);
+    return by_prec(prec, [&](auto z) { return init_t<decltype(z)>(a, n_entries, block, st); });
 }
 
 int launch_observe(int prec, const KArgs &a, int n_entries, int block, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    if (prec == PREC_F64)
-        hipLaunchKernelGGL(k_observe<double>, dim3(n_entries), dim3(block), 0, st, a);
-    else if (prec == PREC_F32)
-        hipLaunchKernelGGL(k_observe<float>, dim3(n_entries), dim3(block), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_observe<__half>, dim3(n_entries), dim3(block), 0, st, a);
-    return (int)hipGetLastError();
+    return by_prec(prec, [&](auto z) {
+        hipLaunchKernelGGL(k_observe<decltype(z)>, dim3(n_entries), dim3(block), 0, st, a);
+        return (int)hipGetLastError();
+    });
 }
 
 int launch_load_raw(int prec, const KArgs &a, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const int g = grid_for((int64_t)Q * a.N);
-    if (prec == PREC_F64)
-        hipLaunchKernelGGL(k_load_raw<double>, dim3(g), dim3(256), 0, st, a);
-    else if (prec == PREC_F32)
-        hipLaunchKernelGGL(k_load_raw<float>, dim3(g), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_load_raw<__half>, dim3(g), dim3(256), 0, st, a);
-    return (int)hipGetLastError();
+    return by_prec(prec, [&](auto z) {
+        hipLaunchKernelGGL(k_load_raw<decltype(z)>, dim3(g), dim3(256), 0, st, a);
+        return (int)hipGetLastError();
+    });
 }
 
 template <typename T, int ODD>
@@ -1015,16 +1049,15 @@ static int aa_step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStrea
     KArgs a = a0;
     if (fused) {
         a.e_off = 0;
-        if ((part == 0 || part == 2) && n_bnd > 0)
-            hipLaunchKernelGGL((k_aa<T, M_FUSED, ODD>), dim3(n_bnd), dim3(block), 0, st, a);
+        if ((part == 0 || part == 2) && n_bnd > 0) launch_aa_mode<T, M_FUSED, ODD>(n_bnd, block, st, a);
     } else {
         if (n_bulk > 0 && (part == 0 || part == 1)) {
             a.e_off = 0;
-            hipLaunchKernelGGL((k_aa<T, M_BULK, ODD>), dim3(n_bulk), dim3(block), 0, st, a);
+            launch_aa_mode<T, M_BULK, ODD>(n_bulk, block, st, a);
         }
         if (n_bnd > 0 && (part == 0 || part == 2)) {
             a.e_off = n_bulk;
-            hipLaunchKernelGGL((k_aa<T, M_BND, ODD>), dim3(n_bnd), dim3(block), 0, st, a);
+            launch_aa_mode<T, M_BND, ODD>(n_bnd, block, st, a);
         }
     }
     if (part == 0 || part == 3) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_AA_SWEEP);
@@ -1034,14 +1067,11 @@ static int aa_step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStrea
 int launch_aa_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part, bool fused,
                    int odd) {
     hipStream_t st = (hipStream_t)stream;
-    if (prec == PREC_F64)
-        return odd ? aa_step_t<double, 1>(a, n_bulk, n_bnd, block, st, part, fused)
-                   : aa_step_t<double, 0>(a, n_bulk, n_bnd, block, st, part, fused);
-    if (prec == PREC_F32)
-        return odd ? aa_step_t<float, 1>(a, n_bulk, n_bnd, block, st, part, fused)
-                   : aa_step_t<float, 0>(a, n_bulk, n_bnd, block, st, part, fused);
-    return odd ? aa_step_t<__half, 1>(a, n_bulk, n_bnd, block, st, part, fused)
-               : aa_step_t<__half, 0>(a, n_bulk, n_bnd, block, st, part, fused);
+    return by_prec(prec, [&](auto z) {
+        using T = decltype(z);
+        return odd ? aa_step_t<T, 1>(a, n_bulk, n_bnd, block, st, part, fused)
+                   : aa_step_t<T, 0>(a, n_bulk, n_bnd, block, st, part, fused);
+    });
 }
 
 template <typename T>
@@ -1055,24 +1085,18 @@ static void aa_moments_t(const KArgs &a, int n_entries, int block, hipStream_t s
 
 int launch_aa_moments(int prec, const KArgs &a, int n_entries, int block, void *stream, int odd) {
     hipStream_t st = (hipStream_t)stream;
-    if (prec == PREC_F64)
-        aa_moments_t<double>(a, n_entries, block, st, odd);
-    else if (prec == PREC_F32)
-        aa_moments_t<float>(a, n_entries, block, st, odd);
-    else
-        aa_moments_t<__half>(a, n_entries, block, st, odd);
-    return (int)hipGetLastError();
+    return by_prec(prec, [&](auto z) {
+        aa_moments_t<decltype(z)>(a, n_entries, block, st, odd);
+        return (int)hipGetLastError();
+    });
 }
 
 int launch_aa_load_odd(int prec, const KArgs &a, int n_entries, int block, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    if (prec == PREC_F64)
-        hipLaunchKernelGGL(k_aa_load_odd<double>, dim3(n_entries), dim3(block), 0, st, a);
-    else if (prec == PREC_F32)
-        hipLaunchKernelGGL(k_aa_load_odd<float>, dim3(n_entries), dim3(block), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_aa_load_odd<__half>, dim3(n_entries), dim3(block), 0, st, a);
-    return (int)hipGetLastError();
+    return by_prec(prec, [&](auto z) {
+        hipLaunchKernelGGL(k_aa_load_odd<decltype(z)>, dim3(n_entries), dim3(block), 0, st, a);
+        return (int)hipGetLastError();
+    });
 }
 
 int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *out, void *stream) {
@@ -1084,13 +1108,10 @@ int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *
 int launch_fill_rest(int prec, const KArgs &a, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const int g = grid_for((int64_t)Q * a.N);
-    if (prec == PREC_F64)
-        hipLaunchKernelGGL(k_fill_rest<double>, dim3(g), dim3(256), 0, st, a);
-    else if (prec == PREC_F32)
-        hipLaunchKernelGGL(k_fill_rest<float>, dim3(g), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_fill_rest<__half>, dim3(g), dim3(256), 0, st, a);
-    return (int)hipGetLastError();
+    return by_prec(prec, [&](auto z) {
+        hipLaunchKernelGGL(k_fill_rest<decltype(z)>, dim3(g), dim3(256), 0, st, a);
+        return (int)hipGetLastError();
+    });
 }
 
 }  // namespace hl

@@ -110,7 +110,7 @@ def test_coupled_1to3_fp64(hl, oracle_mod, mode):
         np.testing.assert_allclose(g.iolet_bc(d, which=1), o.last_bc(d), rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("prec,bound_u,bound_rho", [("f32", 2e-4, 2e-4), ("f16", 0.05, 0.05)])
+@pytest.mark.parametrize("prec,bound_u,bound_rho", [("f32", 2e-4, 2e-4), ("f16", 0.05, 0.05), ("f16w", 0.05, 0.05)])
 def test_offset_storage_errors(hl, oracle_mod, prec, bound_u, bound_rho):
     """FP32 / FP16 storage of f - w rho0 with FP32 arithmetic on the cylinder
     after 1000 steps: the errors against the FP64 oracle are reported and
@@ -123,7 +123,7 @@ def test_offset_storage_errors(hl, oracle_mod, prec, bound_u, bound_rho):
 
 def test_rest_state_stays_exact(hl):
     """Rest state with closed ends: FP64 stays at w_i; offset forms stay 0."""
-    for prec in ("f64", "f32", "f16"):
+    for prec in ("f64", "f32", "f16", "f16w"):
         geo = synth.cylinder(nz=8, q="random", seed=4)
         sc = Scenario([Dom(geo, bouzidi=True, inlets={0: (0.0, (), (), 1.0)}, outlets={1: (1.0, (), (), 1.0)})])
         g = build_gpu(sc, hl, prec)
@@ -144,7 +144,7 @@ def test_graph_and_launch_drivers_are_bitwise_equal(hl):
 
 
 def test_checkpoint_resume_bitwise(hl):
-    for prec in ("f64", "f32", "f16"):
+    for prec in ("f64", "f32", "f16", "f16w"):
         a = build_gpu(c1_scenario(nz=16), hl, prec)
         a.step(60)
         ref = a.populations(0)
@@ -398,7 +398,7 @@ def run_both_order(sc, hl, oracle_mod, steps, order):
     return g, o
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "f16w"])
 def test_aa_checkpoint_graph_and_reload(hl, prec):
     """In-place scheme: graph replay equals plain launches bit for bit from an
     odd start, checkpoints resume bit for bit, and reloading the populations
@@ -432,7 +432,7 @@ def test_aa_checkpoint_graph_and_reload(hl, prec):
 
 
 def test_aa_offset_storage_errors(hl, oracle_mod):
-    for prec, bound in (("f32", 2e-4), ("f16", 0.05)):
+    for prec, bound in (("f32", 2e-4), ("f16", 0.05), ("f16w", 0.05)):
         sc = c1_scenario()
         o = build_oracle(sc, oracle_mod)
         g = build_gpu(sc, hl, prec, order=AA)
@@ -441,3 +441,26 @@ def test_aa_offset_storage_errors(hl, oracle_mod):
         err = errors(g, o)
         print("AA", prec, err, flush=True)
         assert err["e_u"] < bound
+
+
+@pytest.mark.parametrize("order", [0, AA | 8])
+def test_scaled_fp16_slow_flow(hl, oracle_mod, order):
+    """Slow flow at the inlet speed of the paper's human run (about 1.3e-3
+    lattice units per step): the face and edge offsets w_i (3 c_i.u + ...)
+    then sit near the bottom of FP16's normal range, where the plain offset
+    form loses bits.  Storing (f_i - w_i rho0) / w_i keeps them normal; its
+    error against the FP64 oracle is reported beside the plain form's and
+    must not be larger."""
+    geo = synth.cylinder(nz=64, q="half", seed=3)
+    sc = Scenario([Dom(geo, tau=0.8, inlets={0: (1.3e-3, (), (), 1.0)}, outlets={1: (1.0, (), (), 1.0)})])
+    o = build_oracle(sc, oracle_mod)
+    o.step(1500)
+    res = {}
+    for prec in ("f16", "f16w"):
+        g = build_gpu(sc, hl, prec, order=order)
+        g.step(1500)
+        res[prec] = errors(g, o, with_wss=True)
+        print("slow C1", prec, "order", order, res[prec], flush=True)
+        g.close()
+    assert res["f16w"]["e_u"] <= res["f16"]["e_u"]
+    assert res["f16w"]["e_u"] < 0.05

@@ -49,7 +49,7 @@ def test_womersley_full_size(hl, alpha):
     per = wl.meta["period"]
     n0 = int(round(4 * per))
     res = {}
-    for prec in ("f64", "f32", "f16"):
+    for prec in ("f64", "f32", "f16", "f16w"):
         ctx = build_gpu(sc, hl, prec)
         ctx.step(n0)
         err = womersley_error(ctx, wl)
@@ -59,7 +59,7 @@ def test_womersley_full_size(hl, alpha):
               flush=True)
     assert res["f64"][0] < 0.03
     u64 = res["f64"][1]
-    for prec, bound in (("f32", 1e-4), ("f16", 2e-2)):
+    for prec, bound in (("f32", 1e-4), ("f16", 2e-2), ("f16w", 2e-2)):
         e_u = np.abs(res[prec][1] - u64).max() / np.abs(u64).max()
         print(f"womersley alpha={alpha} {prec} vs f64: e_u={e_u:.2e}", flush=True)
         assert e_u < bound
@@ -104,3 +104,53 @@ def test_ensemble_twin(hl, oracle_mod):
     for d in range(len(sc.doms)):
         err = errors(g, o, d)
         assert max(err.values()) <= 1e-12, (d, err)
+
+
+def _areas(geo):
+    codes = geo.nbr[1:]
+    return np.array([int(np.count_nonzero((codes == -2 - k).any(axis=0))) for k in range(len(geo.iolets))])
+
+
+@pytest.mark.parametrize("order", [2, 16 | 8])
+def test_coupled_13_to_1(hl, oracle_mod, order):
+    """13 venous inlets per arterial outlet (the ratio of the leg vasculature,
+    Sec. 3): a depth-2 arterial tree (4 outlets) coupled through the greedy
+    map and Eq. (2) to 52 venous tubes.  The veins are placed, for the map,
+    in a cluster around each outlet, so the greedy map gives every outlet 13.
+    FP64 matches the oracle in both domains; at steady state each artery's
+    outflow reappears in its veins."""
+    from paper_2010_04144_amd import coupling
+    art = synth.tree_geometry(2, 8.0, 20100414 + 13, lam=6.0)
+    ven = synth.tubes(52, radius=3.0, length=16)
+    rng = np.random.default_rng(20100414 + 14)
+    aa, av = _areas(art), _areas(ven)
+    outlets = list(range(1, 5))
+    inlets = list(range(52))
+    oc = np.array([art.iolets[k].centre for k in outlets])
+    sep = min(np.linalg.norm(oc[i] - oc[j]) for i in range(4) for j in range(i + 1, 4))
+    dirs = rng.normal(size=(52, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    pos = [oc[j % 4] + dirs[j] * sep * (0.05 + 0.3 * j / 52) for j in inlets]
+    pairs = coupling.build_pairs(0, outlets, oc, aa[1:5], 1, inlets, pos, av[:52], rng.uniform(0.3, 0.7, 52))
+    counts = [sum(1 for p in pairs if p[1] == i) for i in outlets]
+    assert counts == [13, 13, 13, 13], counts
+    from scenarios import Dom, Scenario
+    sc = Scenario([Dom(art, tau=0.8, bouzidi=True, inlets={0: (0.02, (), (), 1.0)}),
+                   Dom(ven, tau=0.8)], pairs=pairs, mode=0)
+    o = build_oracle(sc, oracle_mod)
+    o.step(300, THREADS)
+    g = build_gpu(sc, hl, "f64", order=order)
+    g.step(300)
+    for d in (0, 1):
+        err = errors(g, o, d)
+        print("13:1 fp64 domain", d, err, flush=True)
+        assert max(err.values()) <= 1e-12, (d, err)
+    g.step(2700)
+    mu_a, _ = g.iolet_stats(0)
+    mu_v, _ = g.iolet_stats(1)
+    for i in outlets:
+        veins = [p[3] for p in pairs if p[1] == i]
+        flux_a = aa[i] * mu_a[i]
+        flux_v = sum(av[j] * mu_v[j] for j in veins)
+        print("artery", i, "veins", len(veins), "flux", flux_a, flux_v, flush=True)
+        assert abs(flux_v - flux_a) / abs(flux_a) < 0.03
