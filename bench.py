@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "f16w": 2}
 TAU = 0.55
 U_IN = 0.01
 
@@ -81,14 +81,17 @@ def measure(ctx, torch, steps):
     return e0.elapsed_time(e1), wall
 
 
-def choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps):
+def choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps, schedule=None):
     """Layout search (site order and streaming scheme, fixed at context
     creation) around the library's own schedule autotuner (work-group size,
-    fused or split launches, XCD order).  Returns the fastest context."""
+    fused or split launches, XCD order), or a fixed schedule (block, flags).
+    Returns the fastest context."""
     best = None
     for order in layouts:
         ctx = make_ctx(hl, geo, prec, torch, order)
-        if autotune_ms > 0:
+        if schedule is not None:
+            ctx.set_schedule(*schedule)
+        elif autotune_ms > 0:
             ctx.autotune(autotune_ms)
         ctx.step(4)
         ms, _ = measure(ctx, torch, probe_steps)
@@ -102,8 +105,9 @@ def choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps):
     return best[1], best[2]
 
 
-def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms, layouts, probe_steps):
-    order, ctx = choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps)
+def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms, layouts, probe_steps,
+                  schedule=None):
+    order, ctx = choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps, schedule)
     ctx.step(warmup)
     ctx.sync()
     t_start = ctx.t
@@ -313,6 +317,8 @@ def main():
     ap.add_argument("--layouts", default="2,8,24",
                     help="hl_create layout flags to search (HL_ORDER_* | HL_SCHEME_AA)")
     ap.add_argument("--probe-steps", type=int, default=200)
+    ap.add_argument("--schedule", default="",
+                    help="fixed schedule BLOCK:FLAGS (HL_SCHED_* bits) instead of the autotuner")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and full-size parity")
@@ -346,10 +352,11 @@ def main():
 
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
     layouts = [int(v) for v in args.layouts.split(",") if v.strip()]
+    schedule = tuple(int(v) for v in args.schedule.split(":")) if args.schedule else None
     runs, fields, tends, chosen = {}, {}, {}, {}
     for p in precs:
         res, u, rho, t_end, order = run_precision(hl, torch, geo, p, args.steps, args.warmup, args.kernel_steps,
-                                                  args.autotune_ms, layouts, args.probe_steps)
+                                                  args.autotune_ms, layouts, args.probe_steps, schedule)
         runs[p] = res
         fields[p] = (u, rho)
         tends[p] = t_end
@@ -399,7 +406,8 @@ def main():
             "box": args.box,
             "segment_length_over_radius": round(geo.meta["lam"], 4),
             "iolets": len(geo.iolets),
-            "storage": {"f64": "FP64", "f32": "FP32 offset f - w rho0", "f16": "FP16 offset f - w rho0"}[head],
+            "storage": {"f64": "FP64", "f32": "FP32 offset f - w rho0", "f16": "FP16 offset f - w rho0",
+                        "f16w": "FP16 (f - w rho0) / w"}[head],
             "arithmetic": "FP64" if head == "f64" else "FP32",
             "scheme": r["scheme"] + ", int32 pull table",
             "layout_flags": r["layout_flags"],

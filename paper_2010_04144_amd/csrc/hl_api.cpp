@@ -252,6 +252,17 @@ hl::KArgs make_args(hl_ctx *c) {
     a.pairs = c->d_pairs;
     a.n_io = (int32_t)c->hio.size();
     a.n_pairs = (int32_t)c->hpairs.size();
+    a.io_e0 = a.io_e1 = 0;
+    for (const auto &io : c->hio) {
+        if (io.e_hi <= io.e_lo) continue;
+        if (a.io_e0 == a.io_e1) {
+            a.io_e0 = io.e_lo;
+            a.io_e1 = io.e_hi;
+        } else {
+            a.io_e0 = std::min(a.io_e0, io.e_lo);
+            a.io_e1 = std::max(a.io_e1, io.e_hi);
+        }
+    }
     a.couple_mode = c->couple_mode;
     a.xcd_remap = (c->sched_flags & HL_SCHED_XCD_REMAP) ? 1 : 0;
     a.ctrl = c->d_ctrl;

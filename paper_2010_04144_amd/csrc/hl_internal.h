@@ -88,6 +88,7 @@ struct KArgs {
     const Entry *entries2;   // bulk entries of 2 x block sites (two sites per lane)
     int32_t aa;              // 1: one in-place lattice (lat0), AA-pattern sweeps
     int32_t n_pairs_blocks;  // > 0: the bulk launch runs the two-sites-per-lane kernel
+    int32_t io_e0, io_e1;    // entry span covering every iolet's entries (empty: io_e0 == io_e1)
     Ctrl *ctrl;
     double *partials;  // [2][n_entries]
     double *stats;     // [2][n_io]: mean u.n, mean rho

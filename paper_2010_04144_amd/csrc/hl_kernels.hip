@@ -63,9 +63,26 @@ __device__ __forceinline__ double ldc(const double *p, int) { return *p; }
 __device__ __forceinline__ float ldc(const float *p, int) { return *p; }
 __device__ __forceinline__ float ldc(const __half *p, int) { return __half2float(*p); }
 __device__ __forceinline__ float ldc(const h16w *p, int row) { return __half2float(p->v) * wgt<float>(row); }
-__device__ __forceinline__ void stc(double *p, double v, int) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ void stc(float *p, float v, int) { __builtin_nontemporal_store(v, p); }
+// NT: non-temporal store (the two-lattice step writes a lattice it does not
+// read); the in-place sweeps store to lines they have just read and keep
+// them cached (NT = false).
+template <bool NT = true>
+__device__ __forceinline__ void stc(double *p, double v, int) {
+    if (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+template <bool NT = true>
+__device__ __forceinline__ void stc(float *p, float v, int) {
+    if (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+template <bool NT = true>
 __device__ __forceinline__ void stc(__half *p, float v, int) { *p = __float2half_rn(v); }
+template <bool NT = true>
 __device__ __forceinline__ void stc(h16w *p, float v, int row) {
     p->v = __float2half_rn(v * (row == 0 ? 3.0f : (row <= 6 ? 18.0f : 36.0f)));
 }
@@ -223,18 +240,42 @@ __device__ double series_at(const IoletDev &io, int64_t t) {
 // FIN_AA_MOMENTS (moments-only pass: f(t) reduced; t kept).
 enum { FIN_STEP = 0, FIN_RAW = 1, FIN_AA_SWEEP = 2, FIN_AA_MOMENTS = 3 };
 
+// Partial sums staged per pass of the iolet sums (16 B each).
+constexpr int FIN_CHUNK = 2048;
+
 __global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
+    __shared__ double2 stage[FIN_CHUNK];
     const int64_t t = a.ctrl->t;
     const int64_t tn = (mode == FIN_STEP) ? t + 1 : t;
     double *mu = a.stats;
     double *mr = a.stats + a.n_io;
+    // Iolet sums over the per-work-group partials.  The partials of the span
+    // of iolet entries pass through LDS in coalesced chunks; each thread adds
+    // its iolets' entries from left to right (the running sums live in mu/mr
+    // between chunks), so the order is that of a plain sequential sum.
+    for (int c0 = a.io_e0; c0 < a.io_e1; c0 += FIN_CHUNK) {
+        const int c1 = min(c0 + FIN_CHUNK, a.io_e1);
+        __syncthreads();
+        for (int e = c0 + (int)threadIdx.x; e < c1; e += blockDim.x)
+            stage[e - c0] = make_double2(a.partials[2 * e], a.partials[2 * e + 1]);
+        __syncthreads();
+        for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
+            const IoletDev &io = a.io[k];
+            const int lo = max(io.e_lo, c0), hi = min(io.e_hi, c1);
+            if (lo >= hi) continue;
+            double su = (c0 > a.io_e0) ? mu[k] : 0.0, sr = (c0 > a.io_e0) ? mr[k] : 0.0;
+            for (int e = lo; e < hi; ++e) {
+                su = su + stage[e - c0].x;
+                sr = sr + stage[e - c0].y;
+            }
+            mu[k] = su;
+            mr[k] = sr;
+        }
+    }
     for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
         const IoletDev &io = a.io[k];
-        double su = 0.0, sr = 0.0;
-        for (int e = io.e_lo; e < io.e_hi; ++e) {
-            su = su + a.partials[2 * e];
-            sr = sr + a.partials[2 * e + 1];
-        }
+        const bool any = io.e_hi > io.e_lo;
+        const double su = any ? mu[k] : 0.0, sr = any ? mr[k] : 0.0;
         mu[k] = io.area > 0.0 ? su / io.area : 0.0;
         mr[k] = io.area > 0.0 ? sr / io.area : RHO0;
         if (!isfinite(su) || !isfinite(sr)) a.ctrl->nan_flag = 1;
@@ -757,21 +798,21 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
             R v = f[mb];
             if (bz && m > 0 && sr[m] == -1 && qv[m] >= R(0.5))
                 v = over(f[mb], R(2) * qv[m]) + (R(1) - over(R(1), R(2) * qv[m])) * f[m];
-            stc(A + (size_t)m * N + s, v, m);
+            stc<false>(A + (size_t)m * N + s, v, m);
         }
     } else {
-        stc(A + s, f[0], 0);
+        stc<false>(A + s, f[0], 0);
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int kb = opp(k);
             const int32_t dst = sr[kb];  // the site at x_s + c_k
             if (dst >= 0) {
-                stc(A + (size_t)k * N + dst, f[k], k);
+                stc<false>(A + (size_t)k * N + dst, f[k], k);
             } else {
                 R v = f[k];
                 if (bz && dst == -1 && qv[kb] >= R(0.5))
                     v = over(f[k], R(2) * qv[kb]) + (R(1) - over(R(1), R(2) * qv[kb])) * f[kb];
-                stc(A + (size_t)kb * N + s, v, kb);
+                stc<false>(A + (size_t)kb * N + s, v, kb);
             }
         }
     }
