@@ -633,10 +633,13 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
 #pragma unroll
         for (int j = 1; j < Q; ++j) {
             const int jb = opp(j);
-            if (BND)
-                x[j] = (sr[j] >= 0) ? ldc(A + (size_t)jb * N + sr[j], jb) : ldc(A + (size_t)j * N + s, j);
-            else
+            if (BND) {
+                // one load from the selected slot (rows j and jb share a weight)
+                const T *p = (sr[j] >= 0) ? A + (size_t)jb * N + sr[j] : A + (size_t)j * N + s;
+                x[j] = ldc(p, j);
+            } else {
                 x[j] = ldc(A + (size_t)jb * N + sr[j], jb);
+            }
         }
     }
     if (!BND) return;
@@ -646,52 +649,53 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
     for (int j = 1; j < Q; ++j) qv[j] = (bz && sr[j] == -1) ? (R)a.bq[(size_t)(j - 1) * a.Nb + b] : R(0.5);
     if (direct) return;
     // boundary rules of the stream t-1 -> t; x[j] holds f*_jb(s, t-1) (or a
-    // final value) for every direction whose upstream voxel is not fluid
+    // final value) for every direction whose upstream voxel is not fluid.
+    // Candidate values are computed for every lane and selected, so the
+    // divergent link mix of boundary sites costs no branches.
     const int64_t p = t - 1;
     const int klass = e.tag & 3;
-    int kind = KIND_INLET;
-    R U = 0, nx = 0, ny = 0, nz = 0, phi = 0;
-    R rho_out = 0, drho_out = 0, ux = 0, uy = 0, uz = 0;
+    if (bz) {
+        // halfway and q >= 1/2 values were stored final; q < 1/2 needs the
+        // second node x_s + c_j, whose population arrived as x[jb] (never
+        // rewritten here: the rule applies only when jb is a fluid link)
+#pragma unroll
+        for (int j = 1; j < Q; ++j) {
+            const int jb = opp(j);
+            const R q = qv[j];
+            const R vw = R(2) * q * x[j] + (R(1) - R(2) * q) * x[jb];
+            x[j] = (sr[j] == -1 && q < R(0.5) && sr[jb] >= 0) ? vw : x[j];
+        }
+    }
     if (klass == K_IOLET) {
         const int g = e.tag >> 2;
         const IoletDev &io = a.io[g];
-        kind = io.kind;
         const double v = a.bc[(p & 1) * a.n_io + g];
-        if (kind == KIND_INLET) {
-            U = (R)v;
-            nx = (R)io.nrm[0];
-            ny = (R)io.nrm[1];
-            nz = (R)io.nrm[2];
-            phi = (R)a.bphi[b];
+        if (io.kind == KIND_INLET) {
+            // Ladd: f_j = f*_jb - 6 w rho0 (c_jb . u_w), u_w = U phi n
+            const R Uphi = (R)v * (R)a.bphi[b];
+            const R nx = (R)io.nrm[0], ny = (R)io.nrm[1], nz = (R)io.nrm[2];
+#pragma unroll
+            for (int j = 1; j < Q; ++j) {
+                const int jb = opp(j);
+                const R cn = R(CX[jb]) * nx + R(CY[jb]) * ny + R(CZ[jb]) * nz;
+                const R vi = x[j] - R(6) * wgt<R>(j) * R(RHO0) * (cn * Uphi);
+                x[j] = (sr[j] <= -2) ? vi : x[j];
+            }
         } else {
-            rho_out = (R)v;
-            drho_out = (R)(v - RHO0);
+            // pressure outlet: equilibrium at rho_out and the site's velocity
+            // of step t-1
+            const R rho_out = (R)v, drho_out = (R)(v - RHO0);
             const R *up = (const R *)((p & 1) ? a.up1 : a.up0);
             const int64_t vi = s - a.IO0;
-            ux = up[vi];
-            uy = up[a.Nio + vi];
-            uz = up[2 * a.Nio + vi];
-        }
-    }
-#pragma unroll
-    for (int j = 1; j < Q; ++j) {
-        if (sr[j] >= 0) continue;
-        const int jb = opp(j);
-        if (sr[j] == -1) {
-            // halfway and q >= 1/2 values were stored final; q < 1/2 needs the
-            // second node x_s + c_j, whose population arrived as x[jb]
-            if (bz && qv[j] < R(0.5) && sr[jb] >= 0) x[j] = R(2) * qv[j] * x[j] + (R(1) - R(2) * qv[j]) * x[jb];
-        } else if (kind == KIND_INLET) {
-            const R cn = R(CX[jb]) * nx + R(CY[jb]) * ny + R(CZ[jb]) * nz;
-            x[j] = x[j] - R(6) * wgt<R>(j) * R(RHO0) * (cn * (U * phi));
-        } else {
-            const R cu = R(CX[j]) * ux + R(CY[j]) * uy + R(CZ[j]) * uz;
+            const R ux = up[vi], uy = up[a.Nio + vi], uz = up[2 * a.Nio + vi];
             const R uu = ux * ux + uy * uy + uz * uz;
-            const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
-            if (OFF)
-                x[j] = wgt<R>(j) * (drho_out + rho_out * poly);
-            else
-                x[j] = wgt<R>(j) * rho_out * (R(1) + poly);
+#pragma unroll
+            for (int j = 1; j < Q; ++j) {
+                const R cu = R(CX[j]) * ux + R(CY[j]) * uy + R(CZ[j]) * uz;
+                const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+                const R vo = OFF ? wgt<R>(j) * (drho_out + rho_out * poly) : wgt<R>(j) * rho_out * (R(1) + poly);
+                x[j] = (sr[j] <= -2) ? vo : x[j];
+            }
         }
     }
 }
@@ -792,28 +796,41 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     if (!ODD) {
         // swapped stores; slot m receives f*_opp(m), or the final wall value
         // of the pulled direction m when x_s - c_m is a Bouzidi wall (q >= 1/2)
+        stc<false>(A + s, f[0], 0);
+        if (bz) {
 #pragma unroll
-        for (int m = 0; m < Q; ++m) {
-            const int mb = opp(m);
-            R v = f[mb];
-            if (bz && m > 0 && sr[m] == -1 && qv[m] >= R(0.5))
-                v = over(f[mb], R(2) * qv[m]) + (R(1) - over(R(1), R(2) * qv[m])) * f[m];
-            stc<false>(A + (size_t)m * N + s, v, m);
+            for (int m = 1; m < Q; ++m) {
+                const int mb = opp(m);
+                const R vb = over(f[mb], R(2) * qv[m]) + (R(1) - over(R(1), R(2) * qv[m])) * f[m];
+                stc<false>(A + (size_t)m * N + s, (sr[m] == -1 && qv[m] >= R(0.5)) ? vb : f[mb], m);
+            }
+        } else {
+#pragma unroll
+            for (int m = 1; m < Q; ++m) stc<false>(A + (size_t)m * N + s, f[opp(m)], m);
         }
     } else {
         stc<false>(A + s, f[0], 0);
+        if (bnd) {
+            // a link whose destination x_s + c_k is not fluid keeps f*_k (or
+            // its final Bouzidi q >= 1/2 wall value) in the site's own slot
+            // opp(k): one store to the selected slot (rows k and opp(k) share
+            // a weight)
 #pragma unroll
-        for (int k = 1; k < Q; ++k) {
-            const int kb = opp(k);
-            const int32_t dst = sr[kb];  // the site at x_s + c_k
-            if (dst >= 0) {
-                stc<false>(A + (size_t)k * N + dst, f[k], k);
-            } else {
+            for (int k = 1; k < Q; ++k) {
+                const int kb = opp(k);
+                const int32_t dst = sr[kb];  // the site at x_s + c_k
                 R v = f[k];
-                if (bz && dst == -1 && qv[kb] >= R(0.5))
-                    v = over(f[k], R(2) * qv[kb]) + (R(1) - over(R(1), R(2) * qv[kb])) * f[kb];
-                stc<false>(A + (size_t)kb * N + s, v, kb);
+                if (bz) {
+                    const R vb = over(f[k], R(2) * qv[kb]) + (R(1) - over(R(1), R(2) * qv[kb])) * f[kb];
+                    v = (dst == -1 && qv[kb] >= R(0.5)) ? vb : v;
+                }
+                T *pd = (dst >= 0) ? A + (size_t)k * N + dst : A + (size_t)kb * N + s;
+                stc<false>(pd, v, k);
             }
+        } else {
+            // bulk site: every neighbour is fluid
+#pragma unroll
+            for (int k = 1; k < Q; ++k) stc<false>(A + (size_t)k * N + sr[opp(k)], f[k], k);
         }
     }
 }
