@@ -113,7 +113,7 @@ struct hl_ctx {
     int steps_per_graph = 16;
     int64_t t_host = 0;
     // layout
-    int64_t N = 0, NB = 0, IO0 = 0, Nb = 0, Nio = 0;
+    int64_t N = 0, NB = 0, IO0 = 0, Nb = 0, Nio = 0, Npad = 0;
     int64_t n_sites = 0, n_bulk_sites = 0, n_io_sites = 0;
     std::vector<Range> ranges;
     std::vector<uint8_t> site_wall;  // interleaved layout: 1 where a site has a boundary link
@@ -234,6 +234,7 @@ hl::KArgs make_args(hl_ctx *c) {
     a.IO0 = c->IO0;
     a.Nb = c->Nb;
     a.Nio = c->Nio;
+    a.Npad = c->Npad;
     a.lat0 = c->lat[0];
     a.lat1 = c->lat[1];
     a.src = c->d_src;
@@ -662,6 +663,7 @@ int commit(hl_ctx *c) {
     }
     align4();
     c->N = pos;  // padded: every range starts, and N ends, on a multiple of 4 slots
+    c->Npad = (c->N + hl::TILE - 1) / hl::TILE * hl::TILE;
     c->Nb = c->N - c->NB;
     c->Nio = c->N - c->IO0;
     const int64_t N = c->N, NB = c->NB, Nb = c->Nb, Nio = c->Nio;
@@ -788,8 +790,8 @@ int commit(hl_ctx *c) {
     int rc;
     for (int p = 0; p < 2; ++p) {
         if (p == 0 || !c->aa) {
-            HIPC(c, hipMalloc(&c->lat[p], (size_t)Q * N * S));
-            c->dev_bytes += (int64_t)((size_t)Q * N * S);
+            HIPC(c, hipMalloc(&c->lat[p], (size_t)Q * c->Npad * S));
+            c->dev_bytes += (int64_t)((size_t)Q * c->Npad * S);
         }
         HIPC(c, hipMalloc(&c->d_up[p], std::max<size_t>((size_t)3 * Nio * A, 8)));
         c->dev_bytes += (int64_t)std::max<size_t>((size_t)3 * Nio * A, 8);
@@ -899,7 +901,7 @@ size_t state_bytes(hl_ctx *c) {
     const size_t S = store_bytes(c->precision), A = arith_bytes(c->precision);
     const size_t nio = c->hio.size();
     const size_t nlat = c->aa ? 1 : 2;
-    return sizeof(StateHeader) + sizeof(hl::Ctrl) + nlat * (size_t)Q * c->N * S + 2 * (size_t)3 * c->Nio * A +
+    return sizeof(StateHeader) + sizeof(hl::Ctrl) + nlat * (size_t)Q * c->Npad * S + 2 * (size_t)3 * c->Nio * A +
            (2 + 2 + 1) * nio * sizeof(double);
 }
 
@@ -1324,8 +1326,8 @@ int hl_get_state(hl_ctx *ctx, void *buf, size_t *bytes) {
     HIPC(ctx, hipMemcpy(p, ctx->d_ctrl, sizeof(hl::Ctrl), hipMemcpyDeviceToHost));
     p += sizeof(hl::Ctrl);
     for (int k = 0; k < (ctx->aa ? 1 : 2); ++k) {
-        HIPC(ctx, hipMemcpy(p, ctx->lat[k], (size_t)Q * ctx->N * S, hipMemcpyDeviceToHost));
-        p += (size_t)Q * ctx->N * S;
+        HIPC(ctx, hipMemcpy(p, ctx->lat[k], (size_t)Q * ctx->Npad * S, hipMemcpyDeviceToHost));
+        p += (size_t)Q * ctx->Npad * S;
     }
     for (int k = 0; k < 2; ++k) {
         if (ctx->Nio) HIPC(ctx, hipMemcpy(p, ctx->d_up[k], (size_t)3 * ctx->Nio * A, hipMemcpyDeviceToHost));
@@ -1362,8 +1364,8 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes) {
     HIPC(ctx, hipMemcpy(ctx->d_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
     p += sizeof(hl::Ctrl);
     for (int k = 0; k < (ctx->aa ? 1 : 2); ++k) {
-        HIPC(ctx, hipMemcpy(ctx->lat[k], p, (size_t)Q * ctx->N * S, hipMemcpyHostToDevice));
-        p += (size_t)Q * ctx->N * S;
+        HIPC(ctx, hipMemcpy(ctx->lat[k], p, (size_t)Q * ctx->Npad * S, hipMemcpyHostToDevice));
+        p += (size_t)Q * ctx->Npad * S;
     }
     for (int k = 0; k < 2; ++k) {
         if (ctx->Nio) HIPC(ctx, hipMemcpy(ctx->d_up[k], p, (size_t)3 * ctx->Nio * A, hipMemcpyHostToDevice));

@@ -21,6 +21,11 @@
 namespace hl {
 
 constexpr int Q = 19;
+// Populations are stored tile-major: tiles of TILE sites, each holding its
+// 19 direction rows contiguously (element (i, s) at
+// ((s / TILE) * Q + i) * TILE + s % TILE); the lattice spans Npad sites.
+constexpr int TILE_SHIFT = 6;
+constexpr int TILE = 1 << TILE_SHIFT;
 constexpr int MAXH = 8;
 constexpr double RHO0 = 1.0;
 
@@ -72,6 +77,7 @@ struct Ctrl {
 
 struct KArgs {
     int64_t N, NB, IO0, Nb, Nio;
+    int64_t Npad;            // N rounded up to whole tiles (lattice extent)
     void *lat0, *lat1;
     const int32_t *src;
     const float *bq;

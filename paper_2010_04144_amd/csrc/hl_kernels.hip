@@ -87,6 +87,14 @@ __device__ __forceinline__ void stc(h16w *p, float v, int row) {
     p->v = __float2half_rn(v * (row == 0 ? 3.0f : (row <= 6 ? 18.0f : 36.0f)));
 }
 
+// Lattice element of direction i at site s.  Sites are grouped in tiles of
+// TILE consecutive sites; a tile holds its 19 direction rows one after the
+// other (tile-major SoA), so a wavefront's accesses to one direction stay a
+// contiguous run while all populations of a tile share a few DRAM pages.
+__device__ __forceinline__ size_t lidx(int i, int64_t s) {
+    return ((((size_t)s >> TILE_SHIFT) * Q + (size_t)i) << TILE_SHIFT) | ((size_t)s & (TILE - 1));
+}
+
 template <typename T>
 __device__ __forceinline__ const T *lat_ptr(const KArgs &a, int64_t parity) {
     return (const T *)((parity & 1) ? a.lat1 : a.lat0);
@@ -117,13 +125,13 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
     int32_t sr[Q];
 #pragma unroll
     for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
-    x[0] = ldc(lin + s, 0);
+    x[0] = ldc(lin + lidx(0, s), 0);
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
         if (BND)
-            x[j] = (sr[j] >= 0) ? ldc(lin + (size_t)j * N + sr[j], j) : R(0);
+            x[j] = (sr[j] >= 0) ? ldc(lin + lidx(j, sr[j]), j) : R(0);
         else
-            x[j] = ldc(lin + (size_t)j * N + sr[j], j);
+            x[j] = ldc(lin + lidx(j, sr[j]), j);
     }
     if (!BND) return;
 
@@ -166,7 +174,7 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
         // f*_i(s) feeds direction ib (bounce-back, Bouzidi, inlet) and, for a
         // Bouzidi wall link, direction i itself (q >= 1/2)
         const bool need = (sr[ib] == -1) || (sr[ib] <= -2 && !outlet) || (bz && sr[i] == -1);
-        own[i] = need ? ldc(lin + (size_t)i * N + s, i) : R(0);
+        own[i] = need ? ldc(lin + lidx(i, s), i) : R(0);
         qv[i] = (bz && sr[i] == -1) ? (R)a.bq[(size_t)(i - 1) * a.Nb + b] : R(0.5);
     }
     // Phase 2: the boundary rules, from registers only.
@@ -383,14 +391,13 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
     const int tid = threadIdx.x;
     const bool act = tid < e.count;
     const int64_t s = (int64_t)e.start + tid;
-    const int64_t N = a.N;
 
     R x[Q];
     if (act) {
         if (MODE == M_RAW) {
             const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s, i);
+            for (int i = 0; i < Q; ++i) x[i] = ldc(raw + lidx(i, s), i);
         } else if (MODE == M_FUSED) {
             if (klass == K_BULK)
                 gather<T, false>(a, e, sg, t, s, x);
@@ -455,7 +462,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
                              (R(3) * (R(CZ[i]) - uz) + R(9) * cu * R(CZ[i])) * Fz;
                 o += (R)sg.guo_pref * wgt<R>(i) * sF;
             }
-            stc(lout + (size_t)i * N + s, o, i);
+            stc(lout + lidx(i, s), o, i);
         }
     }
     if (__ballot(bad) != 0 && (tid & 63) == 0) a.ctrl->nan_flag = 1;
@@ -519,30 +526,30 @@ __global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
 
     R x0[Q], x1[Q];
     if (two) {
-        const V2 v = *(const V2 *)(lin + s);
+        const V2 v = *(const V2 *)(lin + lidx(0, s));  // s even: s, s+1 share a tile
         x0[0] = cvt(v.x);
         x1[0] = cvt(v.y);
     } else {
-        x0[0] = ldc(lin + s, 0);
+        x0[0] = ldc(lin + lidx(0, s), 0);
         x1[0] = R(0);
     }
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
         const int32_t *sp = a.src + (size_t)(j - 1) * N + s;
-        const T *row = lin + (size_t)j * N;
         if (two) {
             const int2v sv = *(const int2v *)sp;
-            if (sv.y == sv.x + 1) {
+            if (sv.y == sv.x + 1 && (sv.x & (TILE - 1)) != TILE - 1) {
+                // adjacent sources in one tile: one vector load
                 V2 v;
-                __builtin_memcpy(&v, row + sv.x, sizeof(V2));
+                __builtin_memcpy(&v, lin + lidx(j, sv.x), sizeof(V2));
                 x0[j] = cvt(v.x);
                 x1[j] = cvt(v.y);
             } else {
-                x0[j] = ldc(row + sv.x, j);
-                x1[j] = ldc(row + sv.y, j);
+                x0[j] = ldc(lin + lidx(j, sv.x), j);
+                x1[j] = ldc(lin + lidx(j, sv.y), j);
             }
         } else {
-            x0[j] = ldc(row + sp[0], j);
+            x0[j] = ldc(lin + lidx(j, sp[0]), j);
             x1[j] = R(0);
         }
     }
@@ -558,7 +565,7 @@ __global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
     if (__ballot(bad0 || bad1) != 0 && (threadIdx.x & 63) == 0) a.ctrl->nan_flag = 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        T *p = lout + (size_t)i * N + s;
+        T *p = lout + lidx(i, s);
         if (two) {
             V2 v;
             v.x = (E)x0[i];
@@ -625,20 +632,20 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
     }
     if (!ODD) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) x[i] = ldc(A + (size_t)i * N + s, i);
+        for (int i = 0; i < Q; ++i) x[i] = ldc(A + lidx(i, s), i);
     } else {
         // (after a reload at an odd step the lattice holds f(t) in the same
         // arrangement, so the same gather reads it back)
-        x[0] = ldc(A + s, 0);
+        x[0] = ldc(A + lidx(0, s), 0);
 #pragma unroll
         for (int j = 1; j < Q; ++j) {
             const int jb = opp(j);
             if (BND) {
                 // one load from the selected slot (rows j and jb share a weight)
-                const T *p = (sr[j] >= 0) ? A + (size_t)jb * N + sr[j] : A + (size_t)j * N + s;
+                const T *p = (sr[j] >= 0) ? A + lidx(jb, sr[j]) : A + lidx(j, s);
                 x[j] = ldc(p, j);
             } else {
-                x[j] = ldc(A + (size_t)jb * N + sr[j], jb);
+                x[j] = ldc(A + lidx(jb, sr[j]), jb);
             }
         }
     }
@@ -775,7 +782,6 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     const SegDev &sg = a.seg[e.seg];
     const bool act = (int)threadIdx.x < e.count;
     const int64_t s = (int64_t)e.start + threadIdx.x;
-    const int64_t N = a.N;
     T *__restrict__ A = (T *)a.lat0;
     R x[Q], qv[Q];
     int32_t sr[Q];
@@ -796,20 +802,20 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     if (!ODD) {
         // swapped stores; slot m receives f*_opp(m), or the final wall value
         // of the pulled direction m when x_s - c_m is a Bouzidi wall (q >= 1/2)
-        stc<false>(A + s, f[0], 0);
+        stc<false>(A + lidx(0, s), f[0], 0);
         if (bz) {
 #pragma unroll
             for (int m = 1; m < Q; ++m) {
                 const int mb = opp(m);
                 const R vb = over(f[mb], R(2) * qv[m]) + (R(1) - over(R(1), R(2) * qv[m])) * f[m];
-                stc<false>(A + (size_t)m * N + s, (sr[m] == -1 && qv[m] >= R(0.5)) ? vb : f[mb], m);
+                stc<false>(A + lidx(m, s), (sr[m] == -1 && qv[m] >= R(0.5)) ? vb : f[mb], m);
             }
         } else {
 #pragma unroll
-            for (int m = 1; m < Q; ++m) stc<false>(A + (size_t)m * N + s, f[opp(m)], m);
+            for (int m = 1; m < Q; ++m) stc<false>(A + lidx(m, s), f[opp(m)], m);
         }
     } else {
-        stc<false>(A + s, f[0], 0);
+        stc<false>(A + lidx(0, s), f[0], 0);
         if (bnd) {
             // a link whose destination x_s + c_k is not fluid keeps f*_k (or
             // its final Bouzidi q >= 1/2 wall value) in the site's own slot
@@ -824,13 +830,13 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
                     const R vb = over(f[k], R(2) * qv[kb]) + (R(1) - over(R(1), R(2) * qv[kb])) * f[kb];
                     v = (dst == -1 && qv[kb] >= R(0.5)) ? vb : v;
                 }
-                T *pd = (dst >= 0) ? A + (size_t)k * N + dst : A + (size_t)kb * N + s;
+                T *pd = (dst >= 0) ? A + lidx(k, dst) : A + lidx(kb, s);
                 stc<false>(pd, v, k);
             }
         } else {
             // bulk site: every neighbour is fluid
 #pragma unroll
-            for (int k = 1; k < Q; ++k) stc<false>(A + (size_t)k * N + sr[opp(k)], f[k], k);
+            for (int k = 1; k < Q; ++k) stc<false>(A + lidx(k, sr[opp(k)]), f[k], k);
         }
     }
 }
@@ -902,7 +908,7 @@ __global__ void __launch_bounds__(256) k_observe(KArgs a) {
     } else if (direct) {
         const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) x[i] = ldc(raw + (size_t)i * N + s, i);
+        for (int i = 0; i < Q; ++i) x[i] = ldc(raw + lidx(i, s), i);
     } else {
         gather<T, true>(a, e, sg, t - 1, s, x);
     }
@@ -971,8 +977,9 @@ __global__ void k_load_raw(KArgs a) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(k / a.N);
+        const int64_t s = k - (int64_t)i * a.N;
         const double v = a.fin[k] - (OFF ? wgt<double>(i) * RHO0 : 0.0);
-        stc(raw + k, (R)v, i);
+        stc(raw + lidx(i, s), (R)v, i);
     }
 }
 
@@ -983,10 +990,11 @@ __global__ void k_fill_rest(KArgs a) {
     constexpr bool OFF = Arith<T>::OFF;
     const int64_t t = a.ctrl->t;
     T *raw = (T *)((!a.aa && ((t + 1) & 1)) ? a.lat1 : a.lat0);
-    const int64_t total = (int64_t)Q * a.N;
+    // every element of the tiled lattice, padding sites included
+    const int64_t total = (int64_t)Q * a.Npad;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(k / a.N);
+        const int i = (int)((k >> TILE_SHIFT) % Q);
         stc(raw + k, OFF ? R(0) : (R)(wgt<double>(i) * RHO0), i);
     }
 }
@@ -1010,15 +1018,15 @@ __global__ void __launch_bounds__(256) k_aa_load_odd(KArgs a) {
     const int64_t s = (int64_t)e.start + threadIdx.x;
     const int64_t N = a.N;
     T *A = (T *)a.lat0;
-    stc(A + s, (R)(a.fin[s] - (OFF ? wgt<double>(0) * RHO0 : 0.0)), 0);
+    stc(A + lidx(0, s), (R)(a.fin[s] - (OFF ? wgt<double>(0) * RHO0 : 0.0)), 0);
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
         const R v = (R)(a.fin[(size_t)j * N + s] - (OFF ? wgt<double>(j) * RHO0 : 0.0));
         const int32_t up = a.src[(size_t)(j - 1) * N + s];
         if (up >= 0)
-            stc(A + (size_t)opp(j) * N + up, v, opp(j));
+            stc(A + lidx(opp(j), up), v, opp(j));
         else
-            stc(A + (size_t)j * N + s, v, j);
+            stc(A + lidx(j, s), v, j);
     }
 }
 
@@ -1165,7 +1173,7 @@ int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *
 
 int launch_fill_rest(int prec, const KArgs &a, void *stream) {
     hipStream_t st = (hipStream_t)stream;
-    const int g = grid_for((int64_t)Q * a.N);
+    const int g = grid_for((int64_t)Q * a.Npad);
     return by_prec(prec, [&](auto z) {
         hipLaunchKernelGGL(k_fill_rest<decltype(z)>, dim3(g), dim3(256), 0, st, a);
         return (int)hipGetLastError();
