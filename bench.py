@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+DRIVES = {0: "launch", 1: "graph"}
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "f16w": 2}
 TAU = 0.55
 U_IN = 0.01
@@ -51,8 +52,12 @@ def bytes_per_site(prec, aa=False):
 
 
 def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_2010_04144_amd", "csrc", "hl_kernels.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the kernel sources (kernels and the layout structs they read)."""
+    h = hashlib.sha256()
+    for name in ("hl_kernels.hip", "hl_internal.h"):
+        with open(os.path.join(ROOT, "paper_2010_04144_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def make_ctx(hl, geo, prec, torch, order=0):
@@ -81,11 +86,14 @@ def measure(ctx, torch, steps):
     return e0.elapsed_time(e1), wall
 
 
-def choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps, schedule=None):
+def choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps, schedule=None, drives=None):
     """Layout search (site order and streaming scheme, fixed at context
     creation) around the library's own schedule autotuner (work-group size,
-    fused or split launches, XCD order), or a fixed schedule (block, flags).
-    Returns the fastest context."""
+    fused or split launches, XCD order), or a fixed schedule (block, flags);
+    then the step drive (plain launches or graph replay) of the fastest.
+    Returns (layout, drive, context)."""
+    if drives is None:
+        drives = (hl.HL_DRIVE_GRAPH, hl.HL_DRIVE_LAUNCH)
     best = None
     for order in layouts:
         ctx = make_ctx(hl, geo, prec, torch, order)
@@ -93,21 +101,26 @@ def choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps, sched
             ctx.set_schedule(*schedule)
         elif autotune_ms > 0:
             ctx.autotune(autotune_ms)
-        ctx.step(4)
-        ms, _ = measure(ctx, torch, probe_steps)
-        log(f"{prec} layout {order}: schedule {ctx.schedule()}, {geo.n * probe_steps / (ms * 1e-3) / 1e6:.0f} MLUPS")
-        if best is None or ms < best[0]:
-            if best is not None:
-                best[2].close()
-            best = (ms, order, ctx)
-        else:
+        for drive in drives:
+            ctx.set_drive(drive)
+            ctx.step(4)
+            ms, _ = measure(ctx, torch, probe_steps)
+            log(f"{prec} layout {order}: schedule {ctx.schedule()}, drive {DRIVES[drive]}, "
+                f"{geo.n * probe_steps / (ms * 1e-3) / 1e6:.0f} MLUPS")
+            if best is None or ms < best[0]:
+                if best is not None and best[3] is not ctx:
+                    best[3].close()
+                best = (ms, order, drive, ctx)
+        if best[3] is not ctx:
             ctx.close()
-    return best[1], best[2]
+    _, order, drive, ctx = best
+    ctx.set_drive(drive)
+    return order, drive, ctx
 
 
 def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms, layouts, probe_steps,
-                  schedule=None):
-    order, ctx = choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps, schedule)
+                  schedule=None, drives=None):
+    order, drive, ctx = choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps, schedule, drives)
     ctx.step(warmup)
     ctx.sync()
     t_start = ctx.t
@@ -140,6 +153,7 @@ def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms
         "scheme": "in-place AA" if aa else "two-lattice pull",
         "block": sched[0],
         "sched_flags": sched[1],
+        "drive": DRIVES[drive],
         "steps_timed_from": t_start,
     }
     log(prec, json.dumps(res))
@@ -204,21 +218,21 @@ def cpu_baseline_and_parity(hl, torch, geo, seconds, threads, order=0):
     return cpu, par
 
 
-def traffic_from_profile(prec, layout, sched):
+def traffic_from_profile(prec, layout, block, sched):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, when it was taken from the same kernel source, layout and
+    summary, when it was taken from the same kernel sources, layout and
     schedule; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    path = os.path.join(ROOT, "profiles", "traffic_branching_artery.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    e = t.get(prec, {})
-    if e.get("layout_flags") != layout or e.get("sched_flags") != sched:
-        return None
-    return e.get("bytes_per_launch")
+    for e in t.get("entries", []):
+        if (e.get("prec"), e.get("layout_flags"), e.get("block"), e.get("sched_flags")) == (prec, layout, block, sched):
+            return e.get("bytes_per_launch")
+    return None
 
 
 def run_multi(hl, torch, args):
@@ -319,6 +333,8 @@ def main():
     ap.add_argument("--probe-steps", type=int, default=200)
     ap.add_argument("--schedule", default="",
                     help="fixed schedule BLOCK:FLAGS (HL_SCHED_* bits) instead of the autotuner")
+    ap.add_argument("--drive", default="", choices=["", "launch", "graph"],
+                    help="fixed step drive instead of timing both")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline and full-size parity")
@@ -353,10 +369,11 @@ def main():
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
     layouts = [int(v) for v in args.layouts.split(",") if v.strip()]
     schedule = tuple(int(v) for v in args.schedule.split(":")) if args.schedule else None
+    drives = {"launch": (hl.HL_DRIVE_LAUNCH,), "graph": (hl.HL_DRIVE_GRAPH,)}.get(args.drive)
     runs, fields, tends, chosen = {}, {}, {}, {}
     for p in precs:
         res, u, rho, t_end, order = run_precision(hl, torch, geo, p, args.steps, args.warmup, args.kernel_steps,
-                                                  args.autotune_ms, layouts, args.probe_steps, schedule)
+                                                  args.autotune_ms, layouts, args.probe_steps, schedule, drives)
         runs[p] = res
         fields[p] = (u, rho)
         tends[p] = t_end
@@ -385,7 +402,7 @@ def main():
     k_sites = geo.n if fused else r["n_bulk"]
     achieved = round(k_sites * B / (k_ms * 1e-3) / 1e9, 1)
     kname = ("k_aa" if r["scheme"].startswith("in-place") else "k_step") + (" fused" if fused else " bulk")
-    traffic = traffic_from_profile(head, r["layout_flags"], r["sched_flags"])
+    traffic = traffic_from_profile(head, r["layout_flags"], r["block"], r["sched_flags"])
     line = {
         "metric": "MLUPS + achieved HBM GB/s (% peak), FP64 vs FP32 at stated error, 1 GPU",
         "value": r["mlups"],
