@@ -241,9 +241,9 @@ def run_multi(hl, torch, args):
     import synth
     t0 = time.perf_counter()
     if args.workload == "coupled":
-        wl = synth.workloads.coupled_pair(lam=args.lam)
+        wl = synth.workloads.coupled_pair(lam=args.lam, progress=log)
     else:
-        wl = synth.workloads.ensemble()
+        wl = synth.workloads.ensemble(progress=log)
     n = sum(d.geo.n for d in wl.domains)
     log(f"{wl.name}: {len(wl.domains)} domains, {n} sites, {len(wl.pairs)} coupled pairs "
         f"({time.perf_counter() - t0:.1f} s)")
@@ -268,23 +268,27 @@ def run_multi(hl, torch, args):
             ctx.commit()
             if args.autotune_ms > 0:
                 ctx.autotune(args.autotune_ms)
-            ctx.step(4)
-            ms, _ = measure(ctx, torch, args.probe_steps)
-            log(f"{prec} layout {order}: schedule {ctx.schedule()}, {n * args.probe_steps / (ms * 1e-3) / 1e6:.0f} MLUPS")
-            if best is None or ms < best[0]:
-                if best is not None:
-                    best[2].close()
-                best = (ms, order, ctx)
-            else:
+            for drive in (hl.HL_DRIVE_GRAPH, hl.HL_DRIVE_LAUNCH):
+                ctx.set_drive(drive)
+                ctx.step(4)
+                ms, _ = measure(ctx, torch, args.probe_steps)
+                log(f"{prec} layout {order}: schedule {ctx.schedule()}, drive {DRIVES[drive]}, "
+                    f"{n * args.probe_steps / (ms * 1e-3) / 1e6:.0f} MLUPS")
+                if best is None or ms < best[0]:
+                    if best is not None and best[2] is not ctx:
+                        best[2].close()
+                    best = (ms, order, ctx, drive)
+            if best[2] is not ctx:
                 ctx.close()
-        _, order, ctx = best
+        _, order, ctx, drive = best
+        ctx.set_drive(drive)
         ctx.step(args.warmup)
         ms, wall = measure(ctx, torch, args.steps)
         mlups = n * args.steps / (ms * 1e-3) / 1e6
         info = ctx.info()
         aa = bool(order & hl.HL_SCHEME_AA)
         out[prec] = {"mlups": round(mlups, 1), "ms_per_step": round(ms / args.steps, 5), "layout_flags": order,
-                     "schedule": list(ctx.schedule()), "alg_GBps": round(mlups * 1e6 * bytes_per_site(prec, aa) / 1e9, 1),
+                     "schedule": list(ctx.schedule()), "drive": DRIVES[drive], "alg_GBps": round(mlups * 1e6 * bytes_per_site(prec, aa) / 1e9, 1),
                      "device_GB": round(info["device_bytes"] / 1e9, 2), "t": ctx.t}
         if wl.pairs:
             mu, _ = ctx.iolet_stats(0)

@@ -79,7 +79,7 @@ def pulsatile(rng, mean=0.01, spread=0.003, harmonics=3, period=None):
 
 
 def coupled_pair(depth=6, r0=48.0, lam=None, vein_scale=1.5, seed=MASTER_SEED + 4, period=4000.0,
-                 tau=0.8, steps=20000):
+                 tau=0.8, steps=20000, progress=None):
     """Arterial tree (root velocity inlet, leaf pressure outlets) coupled 1:1
     at every leaf to the mirrored venous tree of the same seeded topology with
     radii scaled by vein_scale (leaf velocity inlets, root pressure outlet).
@@ -89,7 +89,11 @@ def coupled_pair(depth=6, r0=48.0, lam=None, vein_scale=1.5, seed=MASTER_SEED + 
     if lam is None:
         lam = 8.0
     art = tree_geometry(depth, r0, seed, lam=lam)
+    if progress is not None:
+        progress(f"arterial tree: {art.n} sites")
     ven = tree_geometry(depth, r0, seed, lam=lam, radius_scale=vein_scale, mirror=True, venous=True)
+    if progress is not None:
+        progress(f"venous tree: {ven.n} sites")
     inlet = pulsatile(rng, period=period)
     a = DomainSpec(art, tau, bouzidi=True, inlets={0: inlet})
     v = DomainSpec(ven, tau, bouzidi=True, outlets={0: (1.0, (), (), 1.0)})
@@ -114,16 +118,19 @@ def _iolet_areas(geo):
     return out
 
 
-def ensemble(count=32, lo=5e5, hi=8e6, depth=6, lam=8.0, seed=MASTER_SEED + 5, steps=2000):
+def ensemble(count=32, lo=5e5, hi=8e6, depth=6, lam=8.0, seed=MASTER_SEED + 5, steps=2000, progress=None):
     """count trees with site counts log-uniform in [lo, hi] (root radius scaled
     to hit each target), each with its own tau in [0.52, 0.9] and a seeded
-    3-harmonic inlet waveform with period in [1000, 4000]."""
+    3-harmonic inlet waveform with period in [1000, 4000].  progress(msg) is
+    called after each tree."""
     rng = np.random.default_rng(seed)
     targets = np.exp(rng.uniform(np.log(lo), np.log(hi), size=count))
     doms = []
     for m, nt in enumerate(targets):
         r0 = float((nt / ((depth + 1) * np.pi * lam)) ** (1.0 / 3.0))
         geo = tree_geometry(depth, r0, seed + 100 + m, lam=lam)
+        if progress is not None:
+            progress(f"tree {m + 1}/{count}: {geo.n} sites")
         tau = float(rng.uniform(0.52, 0.9))
         inlet = pulsatile(rng)
         outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}
