@@ -96,6 +96,9 @@ extern "C" {
  * (half the population memory); even steps touch only each site's own
  * populations, odd steps gather and scatter through the pull table */
 #define HL_SCHEME_AA 16u
+/* with HL_ORDER_BRICK: bricks of 32^3 voxels instead of 16^3 (fewer brick faces,
+ * larger groups; HL_E_INVAL without HL_ORDER_BRICK) */
+#define HL_ORDER_BRICK_32 32u
 
 /* schedule flags */
 #define HL_SCHED_XCD_REMAP 1u /* hand each XCD a contiguous range of site blocks */

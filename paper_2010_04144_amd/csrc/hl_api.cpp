@@ -571,8 +571,11 @@ int commit(hl_ctx *c) {
     const bool inter = (c->order_flags & HL_ORDER_INTERLEAVE) != 0;
     const bool brick = (c->order_flags & HL_ORDER_BRICK) != 0;
     if (brick) {
-        // per domain: bricks in lexicographic brick order; inside a brick the
-        // bulk sites, then the wall sites, each in lexicographic order
+        // per domain: bricks (16^3, or 32^3 with HL_ORDER_BRICK_32) in
+        // lexicographic brick order; inside a brick the bulk sites, then the
+        // wall sites, each in lexicographic order
+        const int bb = (c->order_flags & HL_ORDER_BRICK_32) ? 5 : 4;  // log2 of the brick edge
+        const uint64_t bm = (1u << bb) - 1;
         c->site_wall.clear();
         for (int d = 0; d < D; ++d) {
             Domain &dm = c->doms[d];
@@ -587,18 +590,18 @@ int commit(hl_ctx *c) {
                 const uint64_t px = (uint64_t)(dm.coords[x] - mn[0]);
                 const uint64_t py = (uint64_t)(dm.coords[(size_t)dm.n + x] - mn[1]);
                 const uint64_t pz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] - mn[2]);
-                const uint64_t bkey = ((pz >> 4) << 42) | ((py >> 4) << 21) | (px >> 4);
-                const uint64_t lkey = ((pz & 15) << 8) | ((py & 15) << 4) | (px & 15);
+                const uint64_t bkey = ((pz >> bb) << 34) | ((py >> bb) << 17) | (px >> bb);
+                const uint64_t lkey = ((pz & bm) << (2 * bb)) | ((py & bm) << bb) | (px & bm);
                 const uint64_t wall = (k == -2) ? 1 : 0;
-                kv.push_back({(bkey << 13) | (wall << 12) | lkey, x});
+                kv.push_back({(bkey << (3 * bb + 1)) | (wall << (3 * bb)) | lkey, x});
             }
             std::sort(kv.begin(), kv.end());
             size_t m = 0;
             while (m < kv.size()) {
-                const uint64_t grp = kv[m].first >> 12;  // brick and class
+                const uint64_t grp = kv[m].first >> (3 * bb);  // brick and class
                 align4();
                 const int64_t st = pos;
-                while (m < kv.size() && (kv[m].first >> 12) == grp) {
+                while (m < kv.size() && (kv[m].first >> (3 * bb)) == grp) {
                     dm.c2g[kv[m].second] = pos++;
                     ++m;
                 }
@@ -934,8 +937,9 @@ int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     *out = nullptr;
     if (precision < HL_F64 || precision > HL_F16_SCALED) return HL_E_INVAL;
     if (flags & ~(uint64_t)(HL_ORDER_BULK_MORTON | HL_ORDER_BOUNDARY_MORTON | HL_ORDER_INTERLEAVE | HL_ORDER_BRICK |
-                            HL_SCHEME_AA))
+                            HL_SCHEME_AA | HL_ORDER_BRICK_32))
         return HL_E_INVAL;
+    if ((flags & HL_ORDER_BRICK_32) && !(flags & HL_ORDER_BRICK)) return HL_E_INVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HL_E_DEVICE;
     hipDeviceProp_t prop;

@@ -259,64 +259,66 @@ __global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
     double *mr = a.stats + a.n_io;
     // Iolet sums over the per-work-group partials.  The partials of the span
     // of iolet entries pass through LDS in coalesced chunks; each thread adds
-    // its iolets' entries from left to right (the running sums live in mu/mr
-    // between chunks), so the order is that of a plain sequential sum.
-    for (int c0 = a.io_e0; c0 < a.io_e1; c0 += FIN_CHUNK) {
-        const int c1 = min(c0 + FIN_CHUNK, a.io_e1);
-        __syncthreads();
+    // its iolets' entries from left to right (between chunks the running
+    // sums wait in mu/mr), so the order is that of a plain sequential sum.
+    // An iolet's mean, and its next boundary value when it is not coupled,
+    // are final as soon as its sums are; coupled values follow the exchange.
+    const int nchunk = (a.io_e1 - a.io_e0 + FIN_CHUNK - 1) / FIN_CHUNK;
+    for (int c = 0; c < max(nchunk, 1); ++c) {
+        const int c0 = a.io_e0 + c * FIN_CHUNK, c1 = min(c0 + FIN_CHUNK, a.io_e1);
+        if (c > 0) __syncthreads();
         for (int e = c0 + (int)threadIdx.x; e < c1; e += blockDim.x)
             stage[e - c0] = make_double2(a.partials[2 * e], a.partials[2 * e + 1]);
         __syncthreads();
+        const bool last = c + 1 >= nchunk;
         for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
             const IoletDev &io = a.io[k];
             const int lo = max(io.e_lo, c0), hi = min(io.e_hi, c1);
-            if (lo >= hi) continue;
-            double su = (c0 > a.io_e0) ? mu[k] : 0.0, sr = (c0 > a.io_e0) ? mr[k] : 0.0;
+            double su = (c > 0) ? mu[k] : 0.0, sr = (c > 0) ? mr[k] : 0.0;
             for (int e = lo; e < hi; ++e) {
                 su = su + stage[e - c0].x;
                 sr = sr + stage[e - c0].y;
             }
-            mu[k] = su;
-            mr[k] = sr;
-        }
-    }
-    for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
-        const IoletDev &io = a.io[k];
-        const bool any = io.e_hi > io.e_lo;
-        const double su = any ? mu[k] : 0.0, sr = any ? mr[k] : 0.0;
-        mu[k] = io.area > 0.0 ? su / io.area : 0.0;
-        mr[k] = io.area > 0.0 ? sr / io.area : RHO0;
-        if (!isfinite(su) || !isfinite(sr)) a.ctrl->nan_flag = 1;
-    }
-    __syncthreads();
-    const bool fwd = a.couple_mode == COUPLE_BOTH || (tn % 2 == 0);
-    const bool rev = a.couple_mode == COUPLE_BOTH || (tn % 2 == 1);
-    if (fwd) {
-        for (int p = threadIdx.x; p < a.n_pairs; p += blockDim.x) {
-            const PairDev pr = a.pairs[p];
-            const double pb = a.io[pr.in_g].phibar;
-            a.held[pr.in_g] = pb > 0.0 ? pr.s * mu[pr.out_g] / pb : 0.0;
-        }
-    }
-    if (rev) {
-        for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
-            const IoletDev &io = a.io[k];
-            if (io.pair_n == 0) continue;
-            double sum = 0.0;
-            for (int p = io.pair_lo; p < io.pair_lo + io.pair_n; ++p) {
-                const PairDev pr = a.pairs[p];
-                const double pv = (mr[pr.in_g] - RHO0) / 3.0;
-                sum = sum + pv / (1.0 - pr.delta);
+            if (!last) {
+                mu[k] = su;
+                mr[k] = sr;
+                continue;
             }
-            a.held[k] = RHO0 + 3.0 * (sum / (double)io.pair_n);
+            mu[k] = io.area > 0.0 ? su / io.area : 0.0;
+            mr[k] = io.area > 0.0 ? sr / io.area : RHO0;
+            if (!isfinite(su) || !isfinite(sr)) a.ctrl->nan_flag = 1;
+            if (!io.coupled) a.bc[(tn & 1) * a.n_io + k] = series_at(io, tn);
         }
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
-        const IoletDev &io = a.io[k];
-        a.bc[(tn & 1) * a.n_io + k] = io.coupled ? a.held[k] : series_at(io, tn);
+    if (a.n_pairs > 0) {
+        __syncthreads();
+        const bool fwd = a.couple_mode == COUPLE_BOTH || (tn % 2 == 0);
+        const bool rev = a.couple_mode == COUPLE_BOTH || (tn % 2 == 1);
+        if (fwd) {
+            for (int p = threadIdx.x; p < a.n_pairs; p += blockDim.x) {
+                const PairDev pr = a.pairs[p];
+                const double pb = a.io[pr.in_g].phibar;
+                a.held[pr.in_g] = pb > 0.0 ? pr.s * mu[pr.out_g] / pb : 0.0;
+            }
+        }
+        if (rev) {
+            for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
+                const IoletDev &io = a.io[k];
+                if (io.pair_n == 0) continue;
+                double sum = 0.0;
+                for (int p = io.pair_lo; p < io.pair_lo + io.pair_n; ++p) {
+                    const PairDev pr = a.pairs[p];
+                    const double pv = (mr[pr.in_g] - RHO0) / 3.0;
+                    sum = sum + pv / (1.0 - pr.delta);
+                }
+                a.held[k] = RHO0 + 3.0 * (sum / (double)io.pair_n);
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < a.n_io; k += blockDim.x)
+            if (a.io[k].coupled) a.bc[(tn & 1) * a.n_io + k] = a.held[k];
     }
-    __syncthreads();
+    __syncthreads();  // every thread has read ctrl->t
     if (threadIdx.x == 0) {
         if (mode == FIN_STEP || mode == FIN_RAW) {
             a.ctrl->direct = (mode == FIN_RAW);
@@ -785,12 +787,25 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     T *__restrict__ A = (T *)a.lat0;
     R x[Q], qv[Q];
     int32_t sr[Q];
+    // FP16 storage: the wall fractions of a boundary site wait out the
+    // collision in LDS, not in registers (the boundary path's register count
+    // sets the occupancy of the fused sweep: 5 instead of 4 waves per SIMD);
+    // each lane reads back only its own column.  FP32 and FP64 measured
+    // faster with them in registers.
+    constexpr bool QLDS = sizeof(T) == 2;
+    __shared__ float lq[QLDS ? (Q - 1) * 256 : 1];
     const bool bnd = (MODE == M_BND) || (MODE == M_FUSED && klass != K_BULK);
+    const bool bz = bnd && sg.wall_mode == WALL_BOUZIDI;
     if (act) {
-        if (MODE == M_BULK || (MODE == M_FUSED && !bnd))
+        if (MODE == M_BULK || (MODE == M_FUSED && !bnd)) {
             aa_read<T, false, ODD>(a, e, sg, t, s, direct, x, sr, qv);
-        else
+        } else {
             aa_read<T, true, ODD>(a, e, sg, t, s, direct, x, sr, qv);
+            if (QLDS && bz) {
+#pragma unroll
+                for (int j = 1; j < Q; ++j) lq[(j - 1) * 256 + threadIdx.x] = (float)qv[j];
+            }
+        }
     }
     R Fx, Fy, Fz;
     body_force(sg, t, Fx, Fy, Fz);
@@ -798,7 +813,6 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     if (!act) return;
     R(&f)[Q] = x;
     collide_site<R, OFF>(f, sg, Fx, Fy, Fz);
-    const bool bz = bnd && sg.wall_mode == WALL_BOUZIDI;
     if (!ODD) {
         // swapped stores; slot m receives f*_opp(m), or the final wall value
         // of the pulled direction m when x_s - c_m is a Bouzidi wall (q >= 1/2)
@@ -807,8 +821,9 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
 #pragma unroll
             for (int m = 1; m < Q; ++m) {
                 const int mb = opp(m);
-                const R vb = over(f[mb], R(2) * qv[m]) + (R(1) - over(R(1), R(2) * qv[m])) * f[m];
-                stc<false>(A + lidx(m, s), (sr[m] == -1 && qv[m] >= R(0.5)) ? vb : f[mb], m);
+                const R q = QLDS ? (R)lq[(m - 1) * 256 + threadIdx.x] : qv[m];
+                const R vb = over(f[mb], R(2) * q) + (R(1) - over(R(1), R(2) * q)) * f[m];
+                stc<false>(A + lidx(m, s), (sr[m] == -1 && q >= R(0.5)) ? vb : f[mb], m);
             }
         } else {
 #pragma unroll
@@ -827,8 +842,9 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
                 const int32_t dst = sr[kb];  // the site at x_s + c_k
                 R v = f[k];
                 if (bz) {
-                    const R vb = over(f[k], R(2) * qv[kb]) + (R(1) - over(R(1), R(2) * qv[kb])) * f[kb];
-                    v = (dst == -1 && qv[kb] >= R(0.5)) ? vb : v;
+                    const R q = QLDS ? (R)lq[(kb - 1) * 256 + threadIdx.x] : qv[kb];
+                    const R vb = over(f[k], R(2) * q) + (R(1) - over(R(1), R(2) * q)) * f[kb];
+                    v = (dst == -1 && q >= R(0.5)) ? vb : v;
                 }
                 T *pd = (dst >= 0) ? A + lidx(k, dst) : A + lidx(kb, s);
                 stc<false>(pd, v, k);

@@ -99,5 +99,6 @@ def test_bad_arguments_rejected_before_device(hl):
     h = ct.c_void_p()
     assert lib.hl_create(ct.byref(h), 0, 7, 0) == hl.HL_E_INVAL
     assert lib.hl_create(ct.byref(h), 0, 0, 1 << 12) == hl.HL_E_INVAL
+    assert lib.hl_create(ct.byref(h), 0, 0, hl.HL_ORDER_BRICK_32) == hl.HL_E_INVAL  # needs HL_ORDER_BRICK
     assert lib.hl_create(None, 0, 0, 0) == hl.HL_E_INVAL
     lib.hl_destroy(None)

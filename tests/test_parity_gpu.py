@@ -290,7 +290,7 @@ def test_autotune_keeps_state(hl):
 
 
 @pytest.mark.parametrize("order,sched", [(1, 0), (2, 0), (3, 0), (4, 0), (6, 0), (8, 0), (8, 2), (8, 3), (2, 2), (0, 3),
-                                         (2, 4), (2, 5), (8, 4), (0, 4)])
+                                         (2, 4), (2, 5), (8, 4), (0, 4), (8 | 32, 2), (8 | 32, 0)])
 def test_site_orders_agree_with_oracle(hl, oracle_mod, order, sched):
     """Every internal site layout gives the oracle's result: Morton order of
     bulk and/or boundary sites, wall sites interleaved with bulk sites."""
@@ -336,7 +336,7 @@ def test_pair_kernel_is_bitwise_equal_to_single(hl, prec):
 AA = 16
 
 
-@pytest.mark.parametrize("order,sched", [(AA, 0), (AA | 2, 0), (AA | 8, 2), (AA | 8, 3), (AA, 1)])
+@pytest.mark.parametrize("order,sched", [(AA, 0), (AA | 2, 0), (AA | 8, 2), (AA | 8, 3), (AA, 1), (AA | 8 | 32, 3)])
 def test_aa_tree_bouzidi(hl, oracle_mod, order, sched):
     geo = synth.tree_geometry(3, 7.0, 20100416, lam=6.0)
     outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}
