@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 DRIVES = {0: "launch", 1: "graph"}
-STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "f16w": 2}
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "f16w": 2, "f16sr": 2}
 TAU = 0.55
 U_IN = 0.01
 
@@ -428,7 +428,7 @@ def main():
             "segment_length_over_radius": round(geo.meta["lam"], 4),
             "iolets": len(geo.iolets),
             "storage": {"f64": "FP64", "f32": "FP32 offset f - w rho0", "f16": "FP16 offset f - w rho0",
-                        "f16w": "FP16 (f - w rho0) / w"}[head],
+                        "f16w": "FP16 (f - w rho0) / w", "f16sr": "FP16 offset, stochastic rounding"}[head],
             "arithmetic": "FP64" if head == "f64" else "FP32",
             "scheme": r["scheme"] + ", int32 pull table",
             "layout_flags": r["layout_flags"],

@@ -61,6 +61,11 @@ extern "C" {
  * form spends FP16's 11-bit mantissa on values 3x to 12x smaller for the
  * face and edge directions than for the rest population) */
 #define HL_F16_SCALED 3
+/* FP16 storage of f_i - w_i rho0 rounded stochastically on every store (round
+ * up with probability equal to the fraction of the FP16 step below the value;
+ * the random bits are a hash of the lattice element and the step, so runs are
+ * reproducible), FP32 arithmetic */
+#define HL_F16_STOCHASTIC 4
 
 /* wall treatment */
 #define HL_WALL_SBB 0     /* halfway bounce-back */
@@ -105,7 +110,8 @@ extern "C" {
 #define HL_SCHED_FUSED 2u     /* one launch over all work-groups in storage order, each taking the
                                  bulk or the boundary path */
 #define HL_SCHED_PAIRS 4u     /* bulk kernel with two adjacent sites per lane (vector loads/stores);
-                                 ignored with HL_SCHED_FUSED, HL_SCHEME_AA and HL_F16_SCALED */
+                                 ignored with HL_SCHED_FUSED, HL_SCHEME_AA, HL_F16_SCALED and
+                                 HL_F16_STOCHASTIC */
 
 typedef struct hl_ctx hl_ctx;
 
@@ -130,7 +136,7 @@ typedef struct {
 /* ---- context ----------------------------------------------------------- */
 
 /* Create a context on HIP device `device` storing populations in `precision`
- * (HL_F64, HL_F32_OFFSET, HL_F16_OFFSET, HL_F16_SCALED); `flags` is 0 or a combination of
+ * (HL_F64, HL_F32_OFFSET, HL_F16_OFFSET, HL_F16_SCALED, HL_F16_STOCHASTIC); `flags` is 0 or a combination of
  * HL_ORDER_* bits.  Errors: HL_E_INVAL (bad precision or flags), HL_E_DEVICE
  * (no such device, or not gfx950).  *out is NULL on error. */
 int hl_create(hl_ctx **out, int device, int precision, uint64_t flags);

@@ -26,6 +26,7 @@ HL_F64 = 0
 HL_F32_OFFSET = 1
 HL_F16_OFFSET = 2
 HL_F16_SCALED = 3
+HL_F16_STOCHASTIC = 4
 HL_WALL_SBB = 0
 HL_WALL_BOUZIDI = 1
 HL_INLET_VEL = 0

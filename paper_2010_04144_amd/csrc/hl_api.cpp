@@ -246,7 +246,7 @@ hl::KArgs make_args(hl_ctx *c) {
     a.entries = c->d_entries;
     a.entries2 = c->d_entries2;
     a.n_pairs_blocks = ((c->sched_flags & HL_SCHED_PAIRS) && !(c->sched_flags & HL_SCHED_FUSED) && !c->aa &&
-                        c->precision != hl::PREC_F16W)
+                        c->precision != hl::PREC_F16W && c->precision != hl::PREC_F16SR)
                            ? (int32_t)c->entries2.size() : 0;
     a.seg = c->d_seg;
     a.io = c->d_io;
@@ -935,7 +935,7 @@ const char *hl_last_error(const hl_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     if (!out) return HL_E_INVAL;
     *out = nullptr;
-    if (precision < HL_F64 || precision > HL_F16_SCALED) return HL_E_INVAL;
+    if (precision < HL_F64 || precision > HL_F16_STOCHASTIC) return HL_E_INVAL;
     if (flags & ~(uint64_t)(HL_ORDER_BULK_MORTON | HL_ORDER_BOUNDARY_MORTON | HL_ORDER_INTERLEAVE | HL_ORDER_BRICK |
                             HL_SCHEME_AA | HL_ORDER_BRICK_32))
         return HL_E_INVAL;
@@ -1430,7 +1430,7 @@ int hl_autotune(hl_ctx *ctx, int budget_ms) {
     ctx->drive = HL_DRIVE_LAUNCH;
     struct Cand { int block, flags; double ms; };
     std::vector<Cand> cands;
-    const bool pairs_ok = !ctx->aa && ctx->precision != hl::PREC_F16W;
+    const bool pairs_ok = !ctx->aa && ctx->precision != hl::PREC_F16W && ctx->precision != hl::PREC_F16SR;
     for (int b : {64, 128, 256})
         for (int f : {0, (int)HL_SCHED_XCD_REMAP, (int)HL_SCHED_FUSED, (int)(HL_SCHED_FUSED | HL_SCHED_XCD_REMAP),
                       (int)HL_SCHED_PAIRS, (int)(HL_SCHED_PAIRS | HL_SCHED_XCD_REMAP)})

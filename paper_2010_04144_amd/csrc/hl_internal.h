@@ -33,7 +33,7 @@ enum : int32_t { K_BULK = 0, K_WALL = 1, K_IOLET = 2 };
 enum : int32_t { KIND_INLET = 0, KIND_OUTLET = 1 };
 enum : int32_t { WALL_SBB = 0, WALL_BOUZIDI = 1 };
 enum : int32_t { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1 };
-enum : int32_t { PREC_F64 = 0, PREC_F32 = 1, PREC_F16 = 2, PREC_F16W = 3 };
+enum : int32_t { PREC_F64 = 0, PREC_F32 = 1, PREC_F16 = 2, PREC_F16W = 3, PREC_F16SR = 4 };
 
 // One work-group's share of sites: a contiguous internal range inside one
 // domain and one class.  tag = class | (global iolet id << 2).

@@ -59,33 +59,74 @@ template <> struct Arith<double> { using R = double; static constexpr bool OFF =
 struct h16w {
     __half v;
 };
+// FP16 offset storage rounded stochastically on every store.
+struct h16sr {
+    __half v;
+};
+
+// Random bits for stochastic rounding, a function of (lattice element, step)
+// only, so a run is reproducible bit for bit: C. Wellons' "lowbias32"
+// integer hash (hash-prospector, 2018) chained over the step, the high and
+// the low half of the element index.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+template <typename T>
+__device__ __forceinline__ uint32_t rkey(size_t idx, int64_t t) {
+    if constexpr (std::is_same<T, h16sr>::value)
+        return lowbias32((uint32_t)idx ^ lowbias32((uint32_t)(idx >> 32) ^ lowbias32((uint32_t)t)));
+    else
+        return 0u;
+}
+
+// Stochastic rounding to FP16: the value truncated toward zero (lo) or the
+// next FP16 value away from zero (hi), hi with probability (v - lo)/(hi - lo),
+// so the stored value is unbiased.  v - lo is exact in FP32 and hi - lo is a
+// power of two; u is uniform on [0, 1) with 24 bits from r.
+__device__ __forceinline__ __half half_sr(float v, uint32_t r) {
+    const __half lo = __float2half_rz(v);
+    const float flo = __half2float(lo);
+    const float rem = fabsf(v - flo);
+    const __half hi = __ushort_as_half((unsigned short)(__half_as_ushort(lo) + 1));
+    const float ulp = fabsf(__half2float(hi) - flo);
+    const float u = (float)(r >> 8) * 0x1p-24f;
+    return (rem > 0.0f && u * ulp < rem) ? hi : lo;
+}
 __device__ __forceinline__ double ldc(const double *p, int) { return *p; }
 __device__ __forceinline__ float ldc(const float *p, int) { return *p; }
 __device__ __forceinline__ float ldc(const __half *p, int) { return __half2float(*p); }
 __device__ __forceinline__ float ldc(const h16w *p, int row) { return __half2float(p->v) * wgt<float>(row); }
+__device__ __forceinline__ float ldc(const h16sr *p, int) { return __half2float(p->v); }
 // NT: non-temporal store (the two-lattice step writes a lattice it does not
 // read); the in-place sweeps store to lines they have just read and keep
 // them cached (NT = false).
 template <bool NT = true>
-__device__ __forceinline__ void stc(double *p, double v, int) {
+__device__ __forceinline__ void stc(double *p, double v, int, uint32_t = 0) {
     if (NT)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
 }
 template <bool NT = true>
-__device__ __forceinline__ void stc(float *p, float v, int) {
+__device__ __forceinline__ void stc(float *p, float v, int, uint32_t = 0) {
     if (NT)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
 }
 template <bool NT = true>
-__device__ __forceinline__ void stc(__half *p, float v, int) { *p = __float2half_rn(v); }
+__device__ __forceinline__ void stc(__half *p, float v, int, uint32_t = 0) { *p = __float2half_rn(v); }
 template <bool NT = true>
-__device__ __forceinline__ void stc(h16w *p, float v, int row) {
+__device__ __forceinline__ void stc(h16w *p, float v, int row, uint32_t = 0) {
     p->v = __float2half_rn(v * (row == 0 ? 3.0f : (row <= 6 ? 18.0f : 36.0f)));
 }
+template <bool NT = true>
+__device__ __forceinline__ void stc(h16sr *p, float v, int, uint32_t key = 0) { p->v = half_sr(v, key); }
 
 // Lattice element of direction i at site s.  Sites are grouped in tiles of
 // TILE consecutive sites; a tile holds its 19 direction rows one after the
@@ -464,7 +505,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
                              (R(3) * (R(CZ[i]) - uz) + R(9) * cu * R(CZ[i])) * Fz;
                 o += (R)sg.guo_pref * wgt<R>(i) * sF;
             }
-            stc(lout + lidx(i, s), o, i);
+            stc(lout + lidx(i, s), o, i, rkey<T>(lidx(i, s), tn));
         }
     }
     if (__ballot(bad) != 0 && (tid & 63) == 0) a.ctrl->nan_flag = 1;
@@ -589,7 +630,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
 
 template <typename T, int MODE>
 static void launch_mode(int grid, int block, hipStream_t st, const KArgs &a) {
-    if constexpr (MODE == M_BULK && !std::is_same<T, h16w>::value) {
+    if constexpr (MODE == M_BULK && !std::is_same<T, h16w>::value && !std::is_same<T, h16sr>::value) {
         if (a.n_pairs_blocks > 0) {
             hipLaunchKernelGGL((k_bulk2<T>), dim3(a.n_pairs_blocks), dim3(block), 0, st, a);
             return;
@@ -816,21 +857,21 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     if (!ODD) {
         // swapped stores; slot m receives f*_opp(m), or the final wall value
         // of the pulled direction m when x_s - c_m is a Bouzidi wall (q >= 1/2)
-        stc<false>(A + lidx(0, s), f[0], 0);
+        stc<false>(A + lidx(0, s), f[0], 0, rkey<T>(lidx(0, s), t));
         if (bz) {
 #pragma unroll
             for (int m = 1; m < Q; ++m) {
                 const int mb = opp(m);
                 const R q = QLDS ? (R)lq[(m - 1) * 256 + threadIdx.x] : qv[m];
                 const R vb = over(f[mb], R(2) * q) + (R(1) - over(R(1), R(2) * q)) * f[m];
-                stc<false>(A + lidx(m, s), (sr[m] == -1 && q >= R(0.5)) ? vb : f[mb], m);
+                stc<false>(A + lidx(m, s), (sr[m] == -1 && q >= R(0.5)) ? vb : f[mb], m, rkey<T>(lidx(m, s), t));
             }
         } else {
 #pragma unroll
-            for (int m = 1; m < Q; ++m) stc<false>(A + lidx(m, s), f[opp(m)], m);
+            for (int m = 1; m < Q; ++m) stc<false>(A + lidx(m, s), f[opp(m)], m, rkey<T>(lidx(m, s), t));
         }
     } else {
-        stc<false>(A + lidx(0, s), f[0], 0);
+        stc<false>(A + lidx(0, s), f[0], 0, rkey<T>(lidx(0, s), t));
         if (bnd) {
             // a link whose destination x_s + c_k is not fluid keeps f*_k (or
             // its final Bouzidi q >= 1/2 wall value) in the site's own slot
@@ -846,13 +887,13 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
                     const R vb = over(f[k], R(2) * q) + (R(1) - over(R(1), R(2) * q)) * f[kb];
                     v = (dst == -1 && q >= R(0.5)) ? vb : v;
                 }
-                T *pd = (dst >= 0) ? A + lidx(k, dst) : A + lidx(kb, s);
-                stc<false>(pd, v, k);
+                const size_t di = (dst >= 0) ? lidx(k, dst) : lidx(kb, s);
+                stc<false>(A + di, v, k, rkey<T>(di, t));
             }
         } else {
             // bulk site: every neighbour is fluid
 #pragma unroll
-            for (int k = 1; k < Q; ++k) stc<false>(A + lidx(k, sr[opp(k)]), f[k], k);
+            for (int k = 1; k < Q; ++k) stc<false>(A + lidx(k, sr[opp(k)]), f[k], k, rkey<T>(lidx(k, sr[opp(k)]), t));
         }
     }
 }
@@ -995,7 +1036,7 @@ __global__ void k_load_raw(KArgs a) {
         const int i = (int)(k / a.N);
         const int64_t s = k - (int64_t)i * a.N;
         const double v = a.fin[k] - (OFF ? wgt<double>(i) * RHO0 : 0.0);
-        stc(raw + lidx(i, s), (R)v, i);
+        stc(raw + lidx(i, s), (R)v, i, rkey<T>(lidx(i, s), t));
     }
 }
 
@@ -1011,7 +1052,7 @@ __global__ void k_fill_rest(KArgs a) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)((k >> TILE_SHIFT) % Q);
-        stc(raw + k, OFF ? R(0) : (R)(wgt<double>(i) * RHO0), i);
+        stc(raw + k, OFF ? R(0) : (R)(wgt<double>(i) * RHO0), i, rkey<T>((size_t)k, t));
     }
 }
 
@@ -1034,15 +1075,16 @@ __global__ void __launch_bounds__(256) k_aa_load_odd(KArgs a) {
     const int64_t s = (int64_t)e.start + threadIdx.x;
     const int64_t N = a.N;
     T *A = (T *)a.lat0;
-    stc(A + lidx(0, s), (R)(a.fin[s] - (OFF ? wgt<double>(0) * RHO0 : 0.0)), 0);
+    const int64_t t = a.ctrl->t;
+    stc(A + lidx(0, s), (R)(a.fin[s] - (OFF ? wgt<double>(0) * RHO0 : 0.0)), 0, rkey<T>(lidx(0, s), t));
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
         const R v = (R)(a.fin[(size_t)j * N + s] - (OFF ? wgt<double>(j) * RHO0 : 0.0));
         const int32_t up = a.src[(size_t)(j - 1) * N + s];
         if (up >= 0)
-            stc(A + lidx(opp(j), up), v, opp(j));
+            stc(A + lidx(opp(j), up), v, opp(j), rkey<T>(lidx(opp(j), up), t));
         else
-            stc(A + lidx(j, s), v, j);
+            stc(A + lidx(j, s), v, j, rkey<T>(lidx(j, s), t));
     }
 }
 
@@ -1095,7 +1137,8 @@ static int by_prec(int prec, F &&f) {
     case PREC_F64: return f(double());
     case PREC_F32: return f(float());
     case PREC_F16: return f(__half());
-    default: return f(h16w());
+    case PREC_F16W: return f(h16w());
+    default: return f(h16sr());
     }
 }
 

@@ -110,7 +110,8 @@ def test_coupled_1to3_fp64(hl, oracle_mod, mode):
         np.testing.assert_allclose(g.iolet_bc(d, which=1), o.last_bc(d), rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("prec,bound_u,bound_rho", [("f32", 2e-4, 2e-4), ("f16", 0.05, 0.05), ("f16w", 0.05, 0.05)])
+@pytest.mark.parametrize("prec,bound_u,bound_rho", [("f32", 2e-4, 2e-4), ("f16", 0.05, 0.05), ("f16w", 0.05, 0.05),
+                                                    ("f16sr", 0.05, 0.05)])
 def test_offset_storage_errors(hl, oracle_mod, prec, bound_u, bound_rho):
     """FP32 / FP16 storage of f - w rho0 with FP32 arithmetic on the cylinder
     after 1000 steps: the errors against the FP64 oracle are reported and
@@ -123,7 +124,7 @@ def test_offset_storage_errors(hl, oracle_mod, prec, bound_u, bound_rho):
 
 def test_rest_state_stays_exact(hl):
     """Rest state with closed ends: FP64 stays at w_i; offset forms stay 0."""
-    for prec in ("f64", "f32", "f16", "f16w"):
+    for prec in ("f64", "f32", "f16", "f16w", "f16sr"):
         geo = synth.cylinder(nz=8, q="random", seed=4)
         sc = Scenario([Dom(geo, bouzidi=True, inlets={0: (0.0, (), (), 1.0)}, outlets={1: (1.0, (), (), 1.0)})])
         g = build_gpu(sc, hl, prec)
@@ -144,7 +145,7 @@ def test_graph_and_launch_drivers_are_bitwise_equal(hl):
 
 
 def test_checkpoint_resume_bitwise(hl):
-    for prec in ("f64", "f32", "f16", "f16w"):
+    for prec in ("f64", "f32", "f16", "f16w", "f16sr"):
         a = build_gpu(c1_scenario(nz=16), hl, prec)
         a.step(60)
         ref = a.populations(0)
@@ -398,7 +399,7 @@ def run_both_order(sc, hl, oracle_mod, steps, order):
     return g, o
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "f16w"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "f16w", "f16sr"])
 def test_aa_checkpoint_graph_and_reload(hl, prec):
     """In-place scheme: graph replay equals plain launches bit for bit from an
     odd start, checkpoints resume bit for bit, and reloading the populations
@@ -432,7 +433,7 @@ def test_aa_checkpoint_graph_and_reload(hl, prec):
 
 
 def test_aa_offset_storage_errors(hl, oracle_mod):
-    for prec, bound in (("f32", 2e-4), ("f16", 0.05), ("f16w", 0.05)):
+    for prec, bound in (("f32", 2e-4), ("f16", 0.05), ("f16w", 0.05), ("f16sr", 0.05)):
         sc = c1_scenario()
         o = build_oracle(sc, oracle_mod)
         g = build_gpu(sc, hl, prec, order=AA)
@@ -456,7 +457,7 @@ def test_scaled_fp16_slow_flow(hl, oracle_mod, order):
     o = build_oracle(sc, oracle_mod)
     o.step(1500)
     res = {}
-    for prec in ("f16", "f16w"):
+    for prec in ("f16", "f16w", "f16sr"):
         g = build_gpu(sc, hl, prec, order=order)
         g.step(1500)
         res[prec] = errors(g, o, with_wss=True)
@@ -464,3 +465,40 @@ def test_scaled_fp16_slow_flow(hl, oracle_mod, order):
         g.close()
     assert res["f16w"]["e_u"] <= res["f16"]["e_u"]
     assert res["f16w"]["e_u"] < 0.05
+
+
+@pytest.mark.parametrize("order", [0, AA | 8])
+def test_stochastic_fp16_store_is_unbiased(hl, order):
+    """Populations loaded into stochastically rounded FP16 storage come back as
+    one of the two FP16 neighbours of each offset, and their mean over the
+    13,312 sites of the cylinder matches the offset within the sampling
+    error; plain FP16 returns the nearest FP16 value everywhere."""
+    geo = synth.cylinder(nz=64, q="half", seed=3)
+    sc = Scenario([Dom(geo, tau=0.8, inlets={0: (0.0, (), (), 1.0)}, outlets={1: (1.0, (), (), 1.0)})])
+    from scenarios import W
+    delta = 1e-3 * (1.0 + 0.37 * np.arange(19) / 19.0) * np.where(np.arange(19) % 3 == 0, -1.0, 1.0)
+    v = W * delta                                    # offsets, some below FP16's normal range
+    f = np.repeat((W + v)[:, None], geo.n, axis=1)
+    for prec in ("f16", "f16sr"):
+        g = build_gpu(sc, hl, prec, order=order)
+        g.set_populations(0, f)
+        off = g.populations(0) - W[:, None]
+        g.close()
+        for i in range(19):
+            h = np.float16(v[i])
+            if abs(float(h)) > abs(v[i]):
+                lo, hi = np.nextafter(h, np.float16(0)), h
+            else:
+                lo, hi = h, np.nextafter(h, np.float16(np.sign(v[i]) * np.inf))
+            lo, hi = float(lo), float(hi)
+            near_lo = np.abs(off[i] - lo) < 1e-12
+            near_hi = np.abs(off[i] - hi) < 1e-12
+            assert np.all(near_lo | near_hi), (prec, i)
+            if prec == "f16":
+                assert np.all(np.abs(off[i] - float(h)) < 1e-12), i
+            else:
+                p = (abs(v[i]) - abs(lo)) / abs(hi - lo)
+                sd = abs(hi - lo) * np.sqrt(p * (1 - p) / geo.n)
+                m = off[i].mean()
+                print("sr", i, v[i], m, (m - v[i]) / max(sd, 1e-30), flush=True)
+                assert abs(m - v[i]) <= 5 * sd + 1e-15, (i, v[i], m, sd)

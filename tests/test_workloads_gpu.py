@@ -49,7 +49,7 @@ def test_womersley_full_size(hl, alpha):
     per = wl.meta["period"]
     n0 = int(round(4 * per))
     res = {}
-    for prec in ("f64", "f32", "f16", "f16w"):
+    for prec in ("f64", "f32", "f16", "f16w", "f16sr"):
         ctx = build_gpu(sc, hl, prec)
         ctx.step(n0)
         err = womersley_error(ctx, wl)
@@ -59,7 +59,7 @@ def test_womersley_full_size(hl, alpha):
               flush=True)
     assert res["f64"][0] < 0.03
     u64 = res["f64"][1]
-    for prec, bound in (("f32", 1e-4), ("f16", 2e-2), ("f16w", 2e-2)):
+    for prec, bound in (("f32", 1e-4), ("f16", 2e-2), ("f16w", 2e-2), ("f16sr", 2e-2)):
         e_u = np.abs(res[prec][1] - u64).max() / np.abs(u64).max()
         print(f"womersley alpha={alpha} {prec} vs f64: e_u={e_u:.2e}", flush=True)
         assert e_u < bound
