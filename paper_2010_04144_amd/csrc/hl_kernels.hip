@@ -208,7 +208,7 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
     const bool bz = sg.wall_mode == WALL_BOUZIDI;
     const bool outlet = klass == K_IOLET && kind == KIND_OUTLET;
     R own[Q];  // f*_i(s) where a rule reads it
-    R qv[Q];   // wall fraction of the wall link fed into direction j
+    float qv[Q];  // wall fraction of the wall link fed into direction j (stored as float)
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const int ib = opp(i);
@@ -216,7 +216,7 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
         // Bouzidi wall link, direction i itself (q >= 1/2)
         const bool need = (sr[ib] == -1) || (sr[ib] <= -2 && !outlet) || (bz && sr[i] == -1);
         own[i] = need ? ldc(lin + lidx(i, s), i) : R(0);
-        qv[i] = (bz && sr[i] == -1) ? (R)a.bq[(size_t)(i - 1) * a.Nb + b] : R(0.5);
+        qv[i] = (bz && sr[i] == -1) ? a.bq[(size_t)(i - 1) * a.Nb + b] : 0.5f;
     }
     // Phase 2: the boundary rules, from registers only.
 #pragma unroll
@@ -226,7 +226,7 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
         if (sr[j] == -1) {
             // wall link (s, jb): the wall lies at x_s + q c_jb
             if (bz) {
-                const R q = qv[j];
+                const R q = (R)qv[j];
                 if (q < R(0.5)) {
                     // second node x_s - c_jb = x_s + c_j, pulled as x[jb]
                     x[j] = (sr[jb] >= 0) ? R(2) * q * own[jb] + (R(1) - R(2) * q) * x[jb] : own[jb];
@@ -663,7 +663,7 @@ static void launch_mode(int grid, int block, hipStream_t st, const KArgs &a) {
 template <typename T, bool BND, int ODD>
 __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const SegDev &sg, int64_t t, int64_t s,
                                         int direct, typename Arith<T>::R (&x)[Q], int32_t (&sr)[Q],
-                                        typename Arith<T>::R (&qv)[Q]) {
+                                        float (&qv)[Q]) {
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     const T *__restrict__ A = (const T *)a.lat0;
@@ -696,7 +696,7 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
     const bool bz = sg.wall_mode == WALL_BOUZIDI;
     const int64_t b = s - a.NB;
 #pragma unroll
-    for (int j = 1; j < Q; ++j) qv[j] = (bz && sr[j] == -1) ? (R)a.bq[(size_t)(j - 1) * a.Nb + b] : R(0.5);
+    for (int j = 1; j < Q; ++j) qv[j] = (bz && sr[j] == -1) ? a.bq[(size_t)(j - 1) * a.Nb + b] : 0.5f;
     if (direct) return;
     // boundary rules of the stream t-1 -> t; x[j] holds f*_jb(s, t-1) (or a
     // final value) for every direction whose upstream voxel is not fluid.
@@ -711,7 +711,7 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
 #pragma unroll
         for (int j = 1; j < Q; ++j) {
             const int jb = opp(j);
-            const R q = qv[j];
+            const R q = (R)qv[j];
             const R vw = R(2) * q * x[j] + (R(1) - R(2) * q) * x[jb];
             x[j] = (sr[j] == -1 && q < R(0.5) && sr[jb] >= 0) ? vw : x[j];
         }
@@ -826,7 +826,8 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     const bool act = (int)threadIdx.x < e.count;
     const int64_t s = (int64_t)e.start + threadIdx.x;
     T *__restrict__ A = (T *)a.lat0;
-    R x[Q], qv[Q];
+    R x[Q];
+    float qv[Q];
     int32_t sr[Q];
     // FP16 storage: the wall fractions of a boundary site wait out the
     // collision in LDS, not in registers (the boundary path's register count
@@ -844,7 +845,7 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
             aa_read<T, true, ODD>(a, e, sg, t, s, direct, x, sr, qv);
             if (QLDS && bz) {
 #pragma unroll
-                for (int j = 1; j < Q; ++j) lq[(j - 1) * 256 + threadIdx.x] = (float)qv[j];
+                for (int j = 1; j < Q; ++j) lq[(j - 1) * 256 + threadIdx.x] = qv[j];
             }
         }
     }
@@ -862,7 +863,7 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
 #pragma unroll
             for (int m = 1; m < Q; ++m) {
                 const int mb = opp(m);
-                const R q = QLDS ? (R)lq[(m - 1) * 256 + threadIdx.x] : qv[m];
+                const R q = (R)(QLDS ? lq[(m - 1) * 256 + threadIdx.x] : qv[m]);
                 const R vb = over(f[mb], R(2) * q) + (R(1) - over(R(1), R(2) * q)) * f[m];
                 stc<false>(A + lidx(m, s), (sr[m] == -1 && q >= R(0.5)) ? vb : f[mb], m, rkey<T>(lidx(m, s), t));
             }
@@ -883,7 +884,7 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
                 const int32_t dst = sr[kb];  // the site at x_s + c_k
                 R v = f[k];
                 if (bz) {
-                    const R q = QLDS ? (R)lq[(kb - 1) * 256 + threadIdx.x] : qv[kb];
+                    const R q = (R)(QLDS ? lq[(kb - 1) * 256 + threadIdx.x] : qv[kb]);
                     const R vb = over(f[k], R(2) * q) + (R(1) - over(R(1), R(2) * q)) * f[kb];
                     v = (dst == -1 && q >= R(0.5)) ? vb : v;
                 }
@@ -930,7 +931,8 @@ __global__ void __launch_bounds__(256) k_aa_moments(KArgs a) {
     const SegDev &sg = a.seg[e.seg];
     const bool act = (int)threadIdx.x < e.count;
     const int64_t s = (int64_t)e.start + threadIdx.x;
-    R x[Q], qv[Q];
+    R x[Q];
+    float qv[Q];
     int32_t sr[Q];
     if (act) aa_read<T, true, ODD>(a, e, sg, t, s, direct, x, sr, qv);
     R Fx, Fy, Fz;
@@ -956,7 +958,7 @@ __global__ void __launch_bounds__(256) k_observe(KArgs a) {
     const int64_t N = a.N;
     R x[Q];
     if (a.aa) {
-        R qv[Q];
+        float qv[Q];
         int32_t sr[Q];
         if (t & 1)
             aa_read<T, true, 1>(a, e, sg, t, s, direct, x, sr, qv);
