@@ -544,10 +544,12 @@ int commit(hl_ctx *c) {
     // Morton order of the coordinates
     c->ranges.clear();
     int64_t pos = 0;
-    auto align4 = [&]() { pos = (pos + 3) & ~(int64_t)3; };
+    // every group starts on a whole tile: a work-group's wavefronts then own
+    // whole tiles, and no tile row is written by two work-groups
+    auto align_tile = [&]() { pos = (pos + hl::TILE - 1) & ~(int64_t)(hl::TILE - 1); };
     auto place = [&](int d, int32_t key, bool morton) {
         Domain &dm = c->doms[d];
-        align4();
+        align_tile();
         std::vector<int64_t> idx;
         for (int64_t x = 0; x < dm.n; ++x)
             if (cls[d][x] == key) idx.push_back(x);
@@ -599,7 +601,7 @@ int commit(hl_ctx *c) {
             size_t m = 0;
             while (m < kv.size()) {
                 const uint64_t grp = kv[m].first >> (3 * bb);  // brick and class
-                align4();
+                align_tile();
                 const int64_t st = pos;
                 while (m < kv.size() && (kv[m].first >> (3 * bb)) == grp) {
                     dm.c2g[kv[m].second] = pos++;
@@ -621,7 +623,7 @@ int commit(hl_ctx *c) {
             std::vector<int32_t> saved = cd;
             for (auto &v : cd)
                 if (v == -3) v = -1;
-            align4();
+            align_tile();
             const int64_t st = pos;
             place(d, -1, mb);
             cd = saved;
@@ -638,25 +640,25 @@ int commit(hl_ctx *c) {
     } else {
         for (int d = 0; d < D; ++d) {
             c->doms[d].c2g.assign(c->doms[d].n, -1);
-            align4();
+            align_tile();
             const int64_t st = pos;
             if (place(d, -1, mb) > 0) c->ranges.push_back({st, pos - st, d, hl::K_BULK});
         }
-        align4();
+        align_tile();
         c->NB = pos;
         for (int d = 0; d < D; ++d) {
-            align4();
+            align_tile();
             const int64_t st = pos;
             if (place(d, -2, mw) > 0) c->ranges.push_back({st, pos - st, d, hl::K_WALL});
         }
     }
-    align4();
+    align_tile();
     c->IO0 = pos;
     std::vector<int64_t> io_lo(io_count, 0), io_n(io_count, 0);
     for (int d = 0; d < D; ++d) {
         Domain &dm = c->doms[d];
         for (int k = 0; k < dm.n_iolet; ++k) {
-            align4();
+            align_tile();
             const int64_t st = pos;
             place(d, k, mw);
             io_lo[dm.io_base + k] = st;
@@ -664,8 +666,8 @@ int commit(hl_ctx *c) {
             if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_IOLET | ((dm.io_base + k) << 2)});
         }
     }
-    align4();
-    c->N = pos;  // padded: every range starts, and N ends, on a multiple of 4 slots
+    align_tile();
+    c->N = pos;  // padded: every range starts, and N ends, on a whole tile
     c->Npad = (c->N + hl::TILE - 1) / hl::TILE * hl::TILE;
     c->Nb = c->N - c->NB;
     c->Nio = c->N - c->IO0;

@@ -532,12 +532,12 @@ __global__ void __launch_bounds__(256) k_step(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Bulk sites, two adjacent sites per lane.  Range starts and N are multiples
-// of 4, so the pull indices, the rest population and the stores of a lane
-// move as aligned 2-element vectors; a gather moves as one vector (4-byte
+// Bulk sites, two adjacent sites per lane.  Range starts and N are whole
+// tiles (even), so the pull indices, the rest population and the stores of a
+// lane move as aligned 2-element vectors; a gather moves as one vector (4-byte
 // alignment, so the compiler splits it where the target needs that) when the
-// two sources are adjacent, else as two loads.  Same arithmetic as the
-// one-site kernel.
+// two sources are adjacent in one tile, else as two loads.  Same arithmetic
+// as the one-site kernel.
 // ---------------------------------------------------------------------------
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { typedef double elem; typedef double type __attribute__((ext_vector_type(2))); };
