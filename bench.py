@@ -332,7 +332,7 @@ def main():
     ap.add_argument("--precisions", default="f64,f32,f16")
     ap.add_argument("--kernel-steps", type=int, default=50)
     ap.add_argument("--autotune-ms", type=int, default=400)
-    ap.add_argument("--layouts", default="8,24,40",
+    ap.add_argument("--layouts", default="8,24,40,56",
                     help="hl_create layout flags to search (HL_ORDER_* | HL_SCHEME_AA)")
     ap.add_argument("--probe-steps", type=int, default=200)
     ap.add_argument("--schedule", default="",

@@ -109,6 +109,8 @@ extern "C" {
 #define HL_SCHED_XCD_REMAP 1u /* hand each XCD a contiguous range of site blocks */
 #define HL_SCHED_FUSED 2u     /* one launch over all work-groups in storage order, each taking the
                                  bulk or the boundary path */
+#define HL_SCHED_XCD_RUNS 8u  /* with HL_SCHED_XCD_REMAP: runs of 64 consecutive site blocks go to the
+                                 XCDs in turn instead of one contiguous range each */
 #define HL_SCHED_PAIRS 4u     /* bulk kernel with two adjacent sites per lane (vector loads/stores);
                                  ignored with HL_SCHED_FUSED, HL_SCHEME_AA, HL_F16_SCALED and
                                  HL_F16_STOCHASTIC */
@@ -312,9 +314,10 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes);
 
 /* ---- schedule ---------------------------------------------------------------- */
 
-/* Time candidate schedules (work-group size, XCD-aware block order) for about
- * budget_ms and keep the fastest; the dynamic state is saved and restored
- * around the trials. */
+/* Time candidate schedules for about budget_ms and keep the fastest: work-group
+ * size {64, 128, 256} x {split, fused} x {plain, contiguous XCD ranges, XCD
+ * runs}, plus the two-sites-per-lane bulk kernel where it applies.  The dynamic
+ * state is saved and restored around the trials, so results do not change. */
 int hl_autotune(hl_ctx *ctx, int budget_ms);
 int hl_get_schedule(hl_ctx *ctx, int32_t *block_size, int32_t *flags);
 /* block_size in {64, 128, 256}; flags of HL_SCHED_*. */

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (HL_ALTERNATE, HL_BOTH_EACH_STEP, HL_DRIVE_GRAPH, HL_DRIVE_LAUNCH,  # noqa: F401
                    HL_E_DEVICE, HL_E_DIVERGED, HL_E_INVAL, HL_E_NOMEM, HL_E_RANGE, HL_E_STATE,
                    HL_F16_OFFSET, HL_F16_SCALED, HL_F16_STOCHASTIC, HL_F32_OFFSET, HL_F64, HL_INLET_VEL, HL_OK, HL_OUTLET_P,
-                   HL_ORDER_BOUNDARY_MORTON, HL_ORDER_BRICK, HL_ORDER_BRICK_32, HL_ORDER_BULK_MORTON, HL_ORDER_INTERLEAVE, HL_SCHED_FUSED, HL_SCHED_PAIRS, HL_SCHEME_AA, HL_SCHED_XCD_REMAP, HL_W_MACH, HL_W_TAU, HL_WALL_BOUZIDI, HL_WALL_SBB, hl_info)
+                   HL_ORDER_BOUNDARY_MORTON, HL_ORDER_BRICK, HL_ORDER_BRICK_32, HL_ORDER_BULK_MORTON, HL_ORDER_INTERLEAVE, HL_SCHED_FUSED, HL_SCHED_PAIRS, HL_SCHEME_AA, HL_SCHED_XCD_REMAP, HL_SCHED_XCD_RUNS, HL_W_MACH, HL_W_TAU, HL_WALL_BOUZIDI, HL_WALL_SBB, hl_info)
 
 PRECISIONS = {"f64": HL_F64, "f32": HL_F32_OFFSET, "f16": HL_F16_OFFSET, "f16w": HL_F16_SCALED, "f16sr": HL_F16_STOCHASTIC}
 

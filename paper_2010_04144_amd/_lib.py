@@ -42,6 +42,7 @@ HL_ORDER_INTERLEAVE = 4
 HL_ORDER_BRICK = 8
 HL_SCHED_FUSED = 2
 HL_SCHED_PAIRS = 4
+HL_SCHED_XCD_RUNS = 8
 HL_SCHEME_AA = 16
 HL_ORDER_BRICK_32 = 32
 

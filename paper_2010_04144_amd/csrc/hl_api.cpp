@@ -265,7 +265,7 @@ hl::KArgs make_args(hl_ctx *c) {
         }
     }
     a.couple_mode = c->couple_mode;
-    a.xcd_remap = (c->sched_flags & HL_SCHED_XCD_REMAP) ? 1 : 0;
+    a.xcd_remap = !(c->sched_flags & HL_SCHED_XCD_REMAP) ? 0 : ((c->sched_flags & HL_SCHED_XCD_RUNS) ? 64 : 1);
     a.ctrl = c->d_ctrl;
     a.aa = c->aa ? 1 : 0;
     a.partials = c->d_partials;
@@ -1400,8 +1400,10 @@ int hl_set_schedule(hl_ctx *ctx, int32_t block_size, int32_t flags) {
     if (!ctx) return HL_E_INVAL;
     if (block_size != 64 && block_size != 128 && block_size != 256)
         return fail(ctx, HL_E_INVAL, "block size %d not in {64, 128, 256}", block_size);
-    if (flags & ~(int32_t)(HL_SCHED_XCD_REMAP | HL_SCHED_FUSED | HL_SCHED_PAIRS))
+    if (flags & ~(int32_t)(HL_SCHED_XCD_REMAP | HL_SCHED_FUSED | HL_SCHED_PAIRS | HL_SCHED_XCD_RUNS))
         return fail(ctx, HL_E_INVAL, "unknown schedule flags");
+    if ((flags & HL_SCHED_XCD_RUNS) && !(flags & HL_SCHED_XCD_REMAP))
+        return fail(ctx, HL_E_INVAL, "HL_SCHED_XCD_RUNS needs HL_SCHED_XCD_REMAP");
     const bool rebuild = block_size != ctx->block || ((flags ^ ctx->sched_flags) & HL_SCHED_FUSED);
     ctx->block = block_size;
     ctx->sched_flags = flags;
@@ -1433,9 +1435,10 @@ int hl_autotune(hl_ctx *ctx, int budget_ms) {
     struct Cand { int block, flags; double ms; };
     std::vector<Cand> cands;
     const bool pairs_ok = !ctx->aa && ctx->precision != hl::PREC_F16W && ctx->precision != hl::PREC_F16SR;
+    const int R1 = (int)HL_SCHED_XCD_REMAP, RR = (int)(HL_SCHED_XCD_REMAP | HL_SCHED_XCD_RUNS);
+    const int F = (int)HL_SCHED_FUSED, P = (int)HL_SCHED_PAIRS;
     for (int b : {64, 128, 256})
-        for (int f : {0, (int)HL_SCHED_XCD_REMAP, (int)HL_SCHED_FUSED, (int)(HL_SCHED_FUSED | HL_SCHED_XCD_REMAP),
-                      (int)HL_SCHED_PAIRS, (int)(HL_SCHED_PAIRS | HL_SCHED_XCD_REMAP)})
+        for (int f : {0, R1, RR, F, F | R1, F | RR, P, P | R1, P | RR})
             if (pairs_ok || !(f & HL_SCHED_PAIRS)) cands.push_back({b, f, 0.0});
     hipEvent_t e0, e1;
     HIPC(ctx, hipEventCreate(&e0));

@@ -90,7 +90,7 @@ struct KArgs {
     const IoletDev *io;
     const PairDev *pairs;
     int32_t n_io, n_pairs;
-    int32_t couple_mode, xcd_remap;
+    int32_t couple_mode, xcd_remap;  // xcd_remap: 0 none, 1 contiguous eighths, C > 1 runs of C entries
     const Entry *entries2;   // bulk entries of 2 x block sites (two sites per lane)
     int32_t aa;              // 1: one in-place lattice (lat0), AA-pattern sweeps
     int32_t n_pairs_blocks;  // > 0: the bulk launch runs the two-sites-per-lane kernel

@@ -141,15 +141,24 @@ __device__ __forceinline__ const T *lat_ptr(const KArgs &a, int64_t parity) {
     return (const T *)((parity & 1) ? a.lat1 : a.lat0);
 }
 
-// XCD-aware order: work-group b runs on XCD b % 8; hand each XCD a
-// contiguous range of entries so neighbouring sites share an L2.
+// XCD-aware order: work-group b runs on XCD b % 8.  xcd_remap 1: each XCD
+// takes one contiguous eighth of the entries; xcd_remap = C > 1: runs of C
+// consecutive entries go to the XCDs in turn (entries past the last whole
+// round keep their place), so neighbouring sites share an L2 while the XCDs
+// sweep the site list together.
 __device__ __forceinline__ int block_index(int xcd_remap) {
     const int b = blockIdx.x;
     if (!xcd_remap) return b;
     const int G = gridDim.x;
-    const int per = G >> 3, rem = G & 7;
     const int x = b & 7, k = b >> 3;
-    return x * per + (x < rem ? x : rem) + k;
+    if (xcd_remap == 1) {
+        const int per = G >> 3, rem = G & 7;
+        return x * per + (x < rem ? x : rem) + k;
+    }
+    const int C = xcd_remap;
+    const int G8 = G / (8 * C) * (8 * C);
+    if (b >= G8) return b;
+    return ((k / C) * 8 + x) * C + (k % C);
 }
 
 // ---------------------------------------------------------------------------

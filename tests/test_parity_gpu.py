@@ -311,6 +311,28 @@ def test_site_orders_agree_with_oracle(hl, oracle_mod, order, sched):
     check64(errors(g, o))
 
 
+@pytest.mark.parametrize("order,sched", [(8, 1 | 8), (8, 2 | 1 | 8), (16 | 8, 2 | 1 | 8), (2, 4 | 1 | 8)])
+def test_xcd_runs_schedule(hl, oracle_mod, order, sched):
+    """XCD order in runs of 64 work-groups: a tree of about 100k sites in
+    64-lane work-groups has more than 8 x 64 of them, so the run mapping and
+    its tail both occur; FP64 matches the oracle."""
+    geo = synth.tree_geometry(4, 10.0, 20100416, lam=6.0)
+    outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}
+    sc = Scenario([Dom(geo, tau=0.6, bouzidi=True, inlets={0: (0.01, (), (), 1.0)}, outlets=outs)])
+    o = build_oracle(sc, oracle_mod)
+    g = hl.Context(0, "f64", order=order)
+    g.add_domain()
+    g.load_geometry(0, geo)
+    g.set_tau(0, 0.6)
+    g.set_wall_mode(0, hl.HL_WALL_BOUZIDI)
+    g.set_inlet_velocity(0, 0, 0.01)
+    g.set_schedule(64, sched)
+    o.step(101)
+    g.step(101)
+    assert g.info()["n_sites"] > 8 * 64 * 64 + 64 * 10
+    check64(errors(g, o))
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16"])
 def test_pair_kernel_is_bitwise_equal_to_single(hl, prec):
     """The two-sites-per-lane bulk kernel performs the same arithmetic as the
