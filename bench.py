@@ -44,11 +44,12 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def bytes_per_site(prec, aa=False):
-    """Algorithmic HBM bytes of one bulk-site update: 19 populations read and
-    written, plus 18 int32 pull indices (two-lattice pull) or, averaged over
-    an even and an odd step of the in-place scheme, 9."""
-    return 2 * 19 * STORE_BYTES[prec] + (9 if aa else 18) * 4
+def bytes_per_site(prec, aa=False, near=0.0):
+    """Algorithmic HBM bytes of one site update: 19 populations read and
+    written, plus 18 pull indices (two-lattice pull) or, averaged over an even
+    and an odd step of the in-place scheme, 9; an index is 2 bytes for the
+    fraction `near` of sites addressed through int16 deltas, else 4."""
+    return 2 * 19 * STORE_BYTES[prec] + (9 if aa else 18) * (4.0 - 2.0 * near)
 
 
 def kernel_source_hash():
@@ -135,7 +136,8 @@ def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms
     n = geo.n
     mlups = n * steps / (ms * 1e-3) / 1e6
     aa = bool(order & hl.HL_SCHEME_AA)
-    B = bytes_per_site(prec, aa)
+    near = info["n_near"] / info["n_sites"]
+    B = round(bytes_per_site(prec, aa, near), 2)
     bulk_bytes = info["n_bulk"] * B
     res = {
         "mlups": round(mlups, 1),
@@ -147,6 +149,7 @@ def run_precision(hl, torch, geo, prec, steps, warmup, kernel_steps, autotune_ms
         "boundary_kernel_ms": round(kn, 5),
         "bulk_kernel_GBps": round(bulk_bytes / (kb * 1e-3) / 1e9, 1) if kb > 0.01 else None,
         "bytes_per_site": B,
+        "near_fraction": round(near, 4),
         "n_bulk": info["n_bulk"],
         "n_boundary": info["n_boundary"],
         "layout_flags": order,
@@ -287,8 +290,10 @@ def run_multi(hl, torch, args):
         mlups = n * args.steps / (ms * 1e-3) / 1e6
         info = ctx.info()
         aa = bool(order & hl.HL_SCHEME_AA)
+        B = bytes_per_site(prec, aa, info["n_near"] / info["n_sites"])
         out[prec] = {"mlups": round(mlups, 1), "ms_per_step": round(ms / args.steps, 5), "layout_flags": order,
-                     "schedule": list(ctx.schedule()), "drive": DRIVES[drive], "alg_GBps": round(mlups * 1e6 * bytes_per_site(prec, aa) / 1e9, 1),
+                     "schedule": list(ctx.schedule()), "drive": DRIVES[drive], "bytes_per_site": round(B, 2),
+                     "alg_GBps": round(mlups * 1e6 * B / 1e9, 1),
                      "device_GB": round(info["device_bytes"] / 1e9, 2), "t": ctx.t}
         if wl.pairs:
             mu, _ = ctx.iolet_stats(0)

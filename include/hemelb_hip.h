@@ -132,7 +132,8 @@ typedef struct {
     int32_t sched_flags;
     int32_t drive;
     int64_t device_bytes;   /* device memory held by the context */
-    double bytes_per_site;  /* algorithmic HBM bytes per bulk site update */
+    double bytes_per_site;  /* algorithmic HBM bytes per bulk site update (int32 pull indices) */
+    int64_t n_near;         /* bulk sites addressed through int16 pull deltas (18 x 2 B instead of 18 x 4 B) */
 } hl_info;
 
 /* ---- context ----------------------------------------------------------- */

@@ -63,6 +63,7 @@ class hl_info(ct.Structure):
         ("drive", ct.c_int32),
         ("device_bytes", ct.c_int64),
         ("bytes_per_site", ct.c_double),
+        ("n_near", ct.c_int64),
     ]
 
 

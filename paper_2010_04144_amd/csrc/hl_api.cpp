@@ -91,6 +91,7 @@ struct PairH {
 struct Range {
     int64_t start, count;
     int32_t seg, tag;
+    bool mixed = false;  // interleaved bulk and wall sites, split per work-group
 };
 
 }  // namespace
@@ -125,6 +126,8 @@ struct hl_ctx {
     // device memory
     void *lat[2] = {nullptr, nullptr};
     int32_t *d_src = nullptr;
+    int16_t *d_d16 = nullptr;
+    int64_t n_near_sites = 0;
     float *d_bq = nullptr;
     double *d_bphi = nullptr, *d_bnrm = nullptr;
     void *d_up[2] = {nullptr, nullptr};
@@ -193,7 +196,7 @@ void free_device(hl_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
     c->graph_steps = 0;
-    void *ps[] = {c->lat[0], c->lat[1], c->d_src, c->d_bq, c->d_bphi, c->d_bnrm, c->d_up[0], c->d_up[1],
+    void *ps[] = {c->lat[0], c->lat[1], c->d_src, c->d_d16, c->d_bq, c->d_bphi, c->d_bnrm, c->d_up[0], c->d_up[1],
                   c->d_entries, c->d_entries2, c->d_seg, c->d_io, c->d_pairs, c->d_ctrl, c->d_partials, c->d_stats,
                   c->d_bc, c->d_held, c->d_obs, c->d_fbuf};
     for (void *p : ps) dfree(p);
@@ -203,6 +206,7 @@ void free_device(hl_ctx *c) {
     }
     c->lat[0] = c->lat[1] = nullptr;
     c->d_src = nullptr;
+    c->d_d16 = nullptr;
     c->d_bq = nullptr;
     c->d_bphi = c->d_bnrm = nullptr;
     c->d_up[0] = c->d_up[1] = nullptr;
@@ -238,6 +242,7 @@ hl::KArgs make_args(hl_ctx *c) {
     a.lat0 = c->lat[0];
     a.lat1 = c->lat[1];
     a.src = c->d_src;
+    a.d16 = c->d_d16;
     a.bq = c->d_bq;
     a.bphi = c->d_bphi;
     a.up0 = c->d_up[0];
@@ -283,7 +288,6 @@ hl::KArgs make_args(hl_ctx *c) {
 // the interleaved layout a chunk of a mixed range goes to the bulk kernel
 // when none of its sites has a boundary link.  The fused schedule keeps every
 // entry in storage order for a single launch (n_bulk_blocks = 0).
-constexpr int32_t K_MIXED = 3;
 
 void build_entries(hl_ctx *c) {
     std::vector<hl::Entry> bulk, bnd;
@@ -296,12 +300,13 @@ void build_entries(hl_ctx *c) {
             e.count = (int32_t)std::min<int64_t>(c->block, g.count - off);
             e.seg = g.seg;
             e.tag = g.tag;
-            if (klass == K_MIXED) {
+            if (g.mixed) {
                 bool wall = false;
                 for (int32_t k = 0; k < e.count && !wall; ++k) wall = c->site_wall[(size_t)e.start + k] != 0;
                 e.tag = wall ? hl::K_WALL : hl::K_BULK;
             }
-            if ((e.tag & 3) == hl::K_BULK && !(c->sched_flags & HL_SCHED_FUSED))
+            const int ek = e.tag & 3;
+            if ((ek == hl::K_BULK || ek == hl::K_NEAR) && !(c->sched_flags & HL_SCHED_FUSED))
                 bulk.push_back(e);
             else
                 bnd.push_back(e);
@@ -578,6 +583,10 @@ int commit(hl_ctx *c) {
         // wall sites, each in lexicographic order
         const int bb = (c->order_flags & HL_ORDER_BRICK_32) ? 5 : 4;  // log2 of the brick edge
         const uint64_t bm = (1u << bb) - 1;
+        // Bulk sites whose 18 upstream sites all lie in their own brick form a
+        // group of their own (class 0, tagged K_NEAR when their pull deltas
+        // fit in int16, checked once the order is final); other bulk sites
+        // class 1, wall sites class 2.
         c->site_wall.clear();
         for (int d = 0; d < D; ++d) {
             Domain &dm = c->doms[d];
@@ -586,16 +595,27 @@ int commit(hl_ctx *c) {
             int64_t mn[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
             for (int64_t x = 0; x < dm.n; ++x)
                 for (int a = 0; a < 3; ++a) mn[a] = std::min<int64_t>(mn[a], dm.coords[(size_t)a * dm.n + x]);
+            auto brick_of = [&](int64_t x) {
+                const uint64_t px = (uint64_t)(dm.coords[x] - mn[0]);
+                const uint64_t py = (uint64_t)(dm.coords[(size_t)dm.n + x] - mn[1]);
+                const uint64_t pz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] - mn[2]);
+                return ((pz >> bb) << 34) | ((py >> bb) << 17) | (px >> bb);
+            };
             for (int64_t x = 0; x < dm.n; ++x) {
                 const int32_t k = cls[d][x];
                 if (k >= 0) continue;
                 const uint64_t px = (uint64_t)(dm.coords[x] - mn[0]);
                 const uint64_t py = (uint64_t)(dm.coords[(size_t)dm.n + x] - mn[1]);
                 const uint64_t pz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] - mn[2]);
-                const uint64_t bkey = ((pz >> bb) << 34) | ((py >> bb) << 17) | (px >> bb);
+                const uint64_t bkey = brick_of(x);
                 const uint64_t lkey = ((pz & bm) << (2 * bb)) | ((py & bm) << bb) | (px & bm);
-                const uint64_t wall = (k == -2) ? 1 : 0;
-                kv.push_back({(bkey << (3 * bb + 1)) | (wall << (3 * bb)) | lkey, x});
+                uint64_t cl = 2;
+                if (k == -1) {
+                    cl = 0;
+                    for (int j = 1; j < Q && cl == 0; ++j)
+                        if (brick_of(dm.nbr[(size_t)j * dm.n + x]) != bkey) cl = 1;
+                }
+                kv.push_back({(bkey << (3 * bb + 2)) | (cl << (3 * bb)) | lkey, x});
             }
             std::sort(kv.begin(), kv.end());
             size_t m = 0;
@@ -607,7 +627,8 @@ int commit(hl_ctx *c) {
                     dm.c2g[kv[m].second] = pos++;
                     ++m;
                 }
-                c->ranges.push_back({st, pos - st, d, (grp & 1) ? hl::K_WALL : hl::K_BULK});
+                const int cl = (int)(grp & 3);
+                c->ranges.push_back({st, pos - st, d, cl == 0 ? hl::K_NEAR : (cl == 1 ? hl::K_BULK : hl::K_WALL)});
             }
         }
         c->NB = 0;
@@ -627,7 +648,7 @@ int commit(hl_ctx *c) {
             const int64_t st = pos;
             place(d, -1, mb);
             cd = saved;
-            if (pos > st) c->ranges.push_back({st, pos - st, d, K_MIXED});
+            if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_BULK, true});
         }
         c->NB = 0;
         c->site_wall.assign(pos, 0);
@@ -786,6 +807,27 @@ int commit(hl_ctx *c) {
             c->hpairs.push_back(pd);
         }
     }
+    // int16 pull deltas of the K_NEAR groups; a group with a delta beyond
+    // the int16 range falls back to the int32 table (K_BULK)
+    std::vector<int16_t> d16(src.size(), 0);
+    c->n_near_sites = 0;
+    for (Range &g : c->ranges) {
+        if (g.tag != hl::K_NEAR) continue;
+        bool fits = true;
+        for (int j = 1; j < Q && fits; ++j)
+            for (int64_t s = g.start; s < g.start + g.count; ++s) {
+                const int64_t dl = (int64_t)src[(size_t)(j - 1) * N + s] - s;
+                if (dl < -32767 || dl > 32767) {
+                    fits = false;
+                    break;
+                }
+                d16[(size_t)(j - 1) * N + s] = (int16_t)dl;
+            }
+        if (fits)
+            c->n_near_sites += g.count;
+        else
+            g.tag = hl::K_BULK;
+    }
     c->hseg.clear();
     for (auto &d : c->doms) c->hseg.push_back(seg_of(d));
     build_entries(c);
@@ -802,6 +844,7 @@ int commit(hl_ctx *c) {
         c->dev_bytes += (int64_t)std::max<size_t>((size_t)3 * Nio * A, 8);
     }
     if ((rc = dalloc(c, &c->d_src, src.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_d16, d16.size())) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_bq, bq.size())) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_bphi, bphi.size())) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_bnrm, bnrm.size())) != HL_OK) return rc;
@@ -814,6 +857,7 @@ int commit(hl_ctx *c) {
     if ((rc = dalloc(c, &c->d_bc, 2 * nio1)) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_held, nio1)) != HL_OK) return rc;
     HIPC(c, hipMemcpy(c->d_src, src.data(), src.size() * 4, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_d16, d16.data(), d16.size() * 2, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_bq, bq.data(), bq.size() * 4, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_bphi, bphi.data(), bphi.size() * 8, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_bnrm, bnrm.data(), bnrm.size() * 8, hipMemcpyHostToDevice));
@@ -1529,6 +1573,7 @@ int hl_get_info(hl_ctx *ctx, hl_info *out) {
     std::memset(out, 0, sizeof *out);
     out->n_sites = ctx->n_sites;
     out->n_bulk = ctx->n_bulk_sites;
+    out->n_near = ctx->n_near_sites;
     out->n_boundary = ctx->n_sites - ctx->n_bulk_sites;
     out->n_iolet_sites = ctx->n_io_sites;
     out->n_domains = (int32_t)ctx->doms.size();

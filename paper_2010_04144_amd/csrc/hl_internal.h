@@ -29,7 +29,10 @@ constexpr int TILE = 1 << TILE_SHIFT;
 constexpr int MAXH = 8;
 constexpr double RHO0 = 1.0;
 
-enum : int32_t { K_BULK = 0, K_WALL = 1, K_IOLET = 2 };
+// Entry classes: bulk site (every link fluid) with int32 pull indices, wall
+// or iolet boundary site, or bulk site whose upstream sites all lie within
+// 32767 places (int16 pull deltas, K_NEAR).
+enum : int32_t { K_BULK = 0, K_WALL = 1, K_IOLET = 2, K_NEAR = 3 };
 enum : int32_t { KIND_INLET = 0, KIND_OUTLET = 1 };
 enum : int32_t { WALL_SBB = 0, WALL_BOUZIDI = 1 };
 enum : int32_t { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1 };
@@ -80,6 +83,7 @@ struct KArgs {
     int64_t Npad;            // N rounded up to whole tiles (lattice extent)
     void *lat0, *lat1;
     const int32_t *src;
+    const int16_t *d16;      // [18][N] upstream site minus s for K_NEAR sites
     const float *bq;
     const double *bphi;
     void *up0, *up1;

@@ -136,6 +136,23 @@ __device__ __forceinline__ size_t lidx(int i, int64_t s) {
     return ((((size_t)s >> TILE_SHIFT) * Q + (size_t)i) << TILE_SHIFT) | ((size_t)s & (TILE - 1));
 }
 
+// Entry classes whose sites take the bulk path (every link fluid).
+__device__ __forceinline__ bool bulk_class(int klass) { return klass == K_BULK || klass == K_NEAR; }
+
+// Pull indices of a bulk site: from the int16 delta table for a K_NEAR work-
+// group (half the index traffic), else from the int32 table.  The class is
+// uniform over the work-group, so the branch does not diverge.
+__device__ __forceinline__ void pull_indices(const KArgs &a, int klass, int64_t s, int32_t (&sr)[Q]) {
+    const int64_t N = a.N;
+    if (klass == K_NEAR) {
+#pragma unroll
+        for (int j = 1; j < Q; ++j) sr[j] = (int32_t)s + (int32_t)a.d16[(size_t)(j - 1) * N + s];
+    } else {
+#pragma unroll
+        for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ const T *lat_ptr(const KArgs &a, int64_t parity) {
     return (const T *)((parity & 1) ? a.lat1 : a.lat0);
@@ -173,8 +190,12 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
     const T *__restrict__ lin = lat_ptr<T>(a, p);
     const int64_t N = a.N;
     int32_t sr[Q];
+    if (BND) {
 #pragma unroll
-    for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+        for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+    } else {
+        pull_indices(a, e.tag & 3, s, sr);
+    }
     x[0] = ldc(lin + lidx(0, s), 0);
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
@@ -451,7 +472,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) x[i] = ldc(raw + lidx(i, s), i);
         } else if (MODE == M_FUSED) {
-            if (klass == K_BULK)
+            if (bulk_class(klass))
                 gather<T, false>(a, e, sg, t, s, x);
             else
                 gather<T, true>(a, e, sg, t, s, x);
@@ -678,9 +699,11 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
     const T *__restrict__ A = (const T *)a.lat0;
     const int64_t N = a.N;
     // the pull table: needed by odd sweeps (gather/scatter) and by boundary sites
-    if (ODD || BND) {
+    if (BND) {
 #pragma unroll
         for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+    } else if (ODD) {
+        pull_indices(a, e.tag & 3, s, sr);
     }
     if (!ODD) {
 #pragma unroll
@@ -845,7 +868,7 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     // faster with them in registers.
     constexpr bool QLDS = sizeof(T) == 2;
     __shared__ float lq[QLDS ? (Q - 1) * 256 : 1];
-    const bool bnd = (MODE == M_BND) || (MODE == M_FUSED && klass != K_BULK);
+    const bool bnd = (MODE == M_BND) || (MODE == M_FUSED && !bulk_class(klass));
     const bool bz = bnd && sg.wall_mode == WALL_BOUZIDI;
     if (act) {
         if (MODE == M_BULK || (MODE == M_FUSED && !bnd)) {
