@@ -94,8 +94,11 @@ extern "C" {
  * kernel, any other one the boundary kernel */
 #define HL_ORDER_INTERLEAVE 4u
 /* brick-local layout: sites are grouped by 16^3 bricks of the voxel grid;
- * inside a brick, bulk sites come first, then wall sites (lexicographic);
- * iolet sites stay grouped per iolet */
+ * inside a brick the bulk sites whose neighbours all share the brick (their
+ * pull indices are read as int16 deltas, see hl_info.n_near), then the other
+ * bulk sites, then the wall sites, each group in lexicographic order; iolet
+ * sites stay grouped per iolet.  Every group starts on a whole 64-site tile
+ * of the population storage. */
 #define HL_ORDER_BRICK 8u
 /* in-place AA-pattern streaming: one population lattice instead of two
  * (half the population memory); even steps touch only each site's own

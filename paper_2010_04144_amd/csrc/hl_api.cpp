@@ -579,8 +579,8 @@ int commit(hl_ctx *c) {
     const bool brick = (c->order_flags & HL_ORDER_BRICK) != 0;
     if (brick) {
         // per domain: bricks (16^3, or 32^3 with HL_ORDER_BRICK_32) in
-        // lexicographic brick order; inside a brick the bulk sites, then the
-        // wall sites, each in lexicographic order
+        // lexicographic brick order; inside a brick the near bulk sites, the
+        // other bulk sites, then the wall sites, each in lexicographic order
         const int bb = (c->order_flags & HL_ORDER_BRICK_32) ? 5 : 4;  // log2 of the brick edge
         const uint64_t bm = (1u << bb) - 1;
         // Bulk sites whose 18 upstream sites all lie in their own brick form a
