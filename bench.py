@@ -53,9 +53,10 @@ def bytes_per_site(prec, aa=False, near=0.0):
 
 
 def kernel_source_hash():
-    """Hash of the kernel sources (kernels and the layout structs they read)."""
+    """Hash of the library sources: the kernels, the layout structs they read
+    and the host code that orders the sites and builds the schedule."""
     h = hashlib.sha256()
-    for name in ("hl_kernels.hip", "hl_internal.h"):
+    for name in ("hl_kernels.hip", "hl_internal.h", "hl_api.cpp"):
         with open(os.path.join(ROOT, "paper_2010_04144_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -293,7 +293,6 @@ void build_entries(hl_ctx *c) {
     std::vector<hl::Entry> bulk, bnd;
     for (auto &io : c->hio) io.e_lo = io.e_hi = 0;
     for (const Range &g : c->ranges) {
-        const int klass = g.tag & 3;
         for (int64_t off = 0; off < g.count; off += c->block) {
             hl::Entry e;
             e.start = (int32_t)(g.start + off);
@@ -583,10 +582,10 @@ int commit(hl_ctx *c) {
         // other bulk sites, then the wall sites, each in lexicographic order
         const int bb = (c->order_flags & HL_ORDER_BRICK_32) ? 5 : 4;  // log2 of the brick edge
         const uint64_t bm = (1u << bb) - 1;
-        // Bulk sites whose 18 upstream sites all lie in their own brick form a
-        // group of their own (class 0, tagged K_NEAR when their pull deltas
-        // fit in int16, checked once the order is final); other bulk sites
-        // class 1, wall sites class 2.
+        // Bulk sites whose 18 upstream sites all lie in their own brick (and
+        // are not iolet sites) form a group of their own (class 0, tagged
+        // K_NEAR when their pull deltas fit in int16, checked once the order
+        // is final); other bulk sites class 1, wall sites class 2.
         c->site_wall.clear();
         for (int d = 0; d < D; ++d) {
             Domain &dm = c->doms[d];
@@ -611,9 +610,13 @@ int commit(hl_ctx *c) {
                 const uint64_t lkey = ((pz & bm) << (2 * bb)) | ((py & bm) << bb) | (px & bm);
                 uint64_t cl = 2;
                 if (k == -1) {
+                    // near: every upstream site in this brick and not an iolet
+                    // site (iolet groups sit after all bricks, far away)
                     cl = 0;
-                    for (int j = 1; j < Q && cl == 0; ++j)
-                        if (brick_of(dm.nbr[(size_t)j * dm.n + x]) != bkey) cl = 1;
+                    for (int j = 1; j < Q && cl == 0; ++j) {
+                        const int32_t y = dm.nbr[(size_t)j * dm.n + x];
+                        if (brick_of(y) != bkey || cls[d][y] >= 0) cl = 1;
+                    }
                 }
                 kv.push_back({(bkey << (3 * bb + 2)) | (cl << (3 * bb)) | lkey, x});
             }
