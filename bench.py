@@ -354,8 +354,8 @@ def main():
     ap.add_argument("--lam", type=float, default=8.0, help="segment length / radius of the coupled trees")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding paragraph of DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(the step shards by domain or by contiguous site ranges, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
