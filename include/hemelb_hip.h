@@ -95,10 +95,11 @@ extern "C" {
 #define HL_ORDER_INTERLEAVE 4u
 /* brick-local layout: sites are grouped by 16^3 bricks of the voxel grid;
  * inside a brick the bulk sites whose neighbours all share the brick (their
- * pull indices are read as int16 deltas, see hl_info.n_near), then the other
- * bulk sites, then the wall sites, each group in lexicographic order; iolet
- * sites stay grouped per iolet.  Every group starts on a whole 64-site tile
- * of the population storage. */
+ * pull indices are read as int16 deltas, see hl_info.n_near), the other bulk
+ * sites, the wall sites whose fluid neighbours share the brick (int16 deltas
+ * too), the other wall sites, each group in lexicographic order; iolet sites
+ * stay grouped per iolet.  Every group starts on a whole 64-site tile of the
+ * population storage. */
 #define HL_ORDER_BRICK 8u
 /* in-place AA-pattern streaming: one population lattice instead of two
  * (half the population memory); even steps touch only each site's own
@@ -136,7 +137,7 @@ typedef struct {
     int32_t drive;
     int64_t device_bytes;   /* device memory held by the context */
     double bytes_per_site;  /* algorithmic HBM bytes per bulk site update (int32 pull indices) */
-    int64_t n_near;         /* bulk sites addressed through int16 pull deltas (18 x 2 B instead of 18 x 4 B) */
+    int64_t n_near;         /* sites addressed through int16 pull deltas (18 x 2 B instead of 18 x 4 B) */
 } hl_info;
 
 /* ---- context ----------------------------------------------------------- */

@@ -304,7 +304,7 @@ void build_entries(hl_ctx *c) {
                 for (int32_t k = 0; k < e.count && !wall; ++k) wall = c->site_wall[(size_t)e.start + k] != 0;
                 e.tag = wall ? hl::K_WALL : hl::K_BULK;
             }
-            const int ek = e.tag & 3;
+            const int ek = hl::tag_class(e.tag);
             if ((ek == hl::K_BULK || ek == hl::K_NEAR) && !(c->sched_flags & HL_SCHED_FUSED))
                 bulk.push_back(e);
             else
@@ -329,8 +329,8 @@ void build_entries(hl_ctx *c) {
     c->n_bnd_blocks = (int)bnd.size();
     for (int e = 0; e < (int)c->entries.size(); ++e) {
         const hl::Entry &en = c->entries[e];
-        if ((en.tag & 3) != hl::K_IOLET) continue;
-        auto &io = c->hio[en.tag >> 2];
+        if (hl::tag_class(en.tag) != hl::K_IOLET) continue;
+        auto &io = c->hio[hl::tag_iolet(en.tag)];
         if (io.e_hi == 0) io.e_lo = e;
         io.e_hi = e + 1;
     }
@@ -585,7 +585,9 @@ int commit(hl_ctx *c) {
         // Bulk sites whose 18 upstream sites all lie in their own brick (and
         // are not iolet sites) form a group of their own (class 0, tagged
         // K_NEAR when their pull deltas fit in int16, checked once the order
-        // is final); other bulk sites class 1, wall sites class 2.
+        // is final); other bulk sites class 1; wall sites whose fluid upstream
+        // sites satisfy the same condition class 2 (K_NEARWALL), other wall
+        // sites class 3.
         c->site_wall.clear();
         for (int d = 0; d < D; ++d) {
             Domain &dm = c->doms[d];
@@ -608,16 +610,14 @@ int commit(hl_ctx *c) {
                 const uint64_t pz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] - mn[2]);
                 const uint64_t bkey = brick_of(x);
                 const uint64_t lkey = ((pz & bm) << (2 * bb)) | ((py & bm) << bb) | (px & bm);
-                uint64_t cl = 2;
-                if (k == -1) {
-                    // near: every upstream site in this brick and not an iolet
-                    // site (iolet groups sit after all bricks, far away)
-                    cl = 0;
-                    for (int j = 1; j < Q && cl == 0; ++j) {
-                        const int32_t y = dm.nbr[(size_t)j * dm.n + x];
-                        if (brick_of(y) != bkey || cls[d][y] >= 0) cl = 1;
-                    }
+                // near: every fluid upstream site in this brick and not an
+                // iolet site (iolet groups sit after all bricks, far away)
+                bool near = true;
+                for (int j = 1; j < Q && near; ++j) {
+                    const int32_t y = dm.nbr[(size_t)j * dm.n + x];
+                    if (y >= 0 && (brick_of(y) != bkey || cls[d][y] >= 0)) near = false;
                 }
+                const uint64_t cl = (k == -1) ? (near ? 0 : 1) : (near ? 2 : 3);
                 kv.push_back({(bkey << (3 * bb + 2)) | (cl << (3 * bb)) | lkey, x});
             }
             std::sort(kv.begin(), kv.end());
@@ -630,8 +630,8 @@ int commit(hl_ctx *c) {
                     dm.c2g[kv[m].second] = pos++;
                     ++m;
                 }
-                const int cl = (int)(grp & 3);
-                c->ranges.push_back({st, pos - st, d, cl == 0 ? hl::K_NEAR : (cl == 1 ? hl::K_BULK : hl::K_WALL)});
+                static const int32_t tag_of[4] = {hl::K_NEAR, hl::K_BULK, hl::K_NEARWALL, hl::K_WALL};
+                c->ranges.push_back({st, pos - st, d, tag_of[grp & 3]});
             }
         }
         c->NB = 0;
@@ -687,7 +687,7 @@ int commit(hl_ctx *c) {
             place(d, k, mw);
             io_lo[dm.io_base + k] = st;
             io_n[dm.io_base + k] = pos - st;
-            if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_IOLET | ((dm.io_base + k) << 2)});
+            if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_IOLET | ((dm.io_base + k) << hl::CLASS_BITS)});
         }
     }
     align_tile();
@@ -810,26 +810,28 @@ int commit(hl_ctx *c) {
             c->hpairs.push_back(pd);
         }
     }
-    // int16 pull deltas of the K_NEAR groups; a group with a delta beyond
-    // the int16 range falls back to the int32 table (K_BULK)
+    // int16 pull deltas of the K_NEAR and K_NEARWALL groups (INT16_MIN for a
+    // wall link); a group with a delta beyond the int16 range falls back to
+    // the int32 table (K_BULK or K_WALL)
     std::vector<int16_t> d16(src.size(), 0);
     c->n_near_sites = 0;
     for (Range &g : c->ranges) {
-        if (g.tag != hl::K_NEAR) continue;
+        if (g.tag != hl::K_NEAR && g.tag != hl::K_NEARWALL) continue;
         bool fits = true;
         for (int j = 1; j < Q && fits; ++j)
             for (int64_t s = g.start; s < g.start + g.count; ++s) {
-                const int64_t dl = (int64_t)src[(size_t)(j - 1) * N + s] - s;
-                if (dl < -32767 || dl > 32767) {
+                const int32_t v = src[(size_t)(j - 1) * N + s];
+                const int64_t dl = (int64_t)v - s;
+                if (v < -1 || (v >= 0 && (dl < -32767 || dl > 32767))) {
                     fits = false;
                     break;
                 }
-                d16[(size_t)(j - 1) * N + s] = (int16_t)dl;
+                d16[(size_t)(j - 1) * N + s] = (v == -1) ? (int16_t)INT16_MIN : (int16_t)dl;
             }
         if (fits)
             c->n_near_sites += g.count;
         else
-            g.tag = hl::K_BULK;
+            g.tag = (g.tag == hl::K_NEAR) ? hl::K_BULK : hl::K_WALL;
     }
     c->hseg.clear();
     for (auto &d : c->doms) c->hseg.push_back(seg_of(d));

@@ -30,16 +30,20 @@ constexpr int MAXH = 8;
 constexpr double RHO0 = 1.0;
 
 // Entry classes: bulk site (every link fluid) with int32 pull indices, wall
-// or iolet boundary site, or bulk site whose upstream sites all lie within
-// 32767 places (int16 pull deltas, K_NEAR).
-enum : int32_t { K_BULK = 0, K_WALL = 1, K_IOLET = 2, K_NEAR = 3 };
+// or iolet boundary site, bulk site whose upstream sites all lie within 32767
+// places (int16 pull deltas, K_NEAR), or wall site whose fluid upstream sites
+// do (int16 deltas, INT16_MIN for a wall link, K_NEARWALL).
+enum : int32_t { K_BULK = 0, K_WALL = 1, K_IOLET = 2, K_NEAR = 3, K_NEARWALL = 4 };
+constexpr int CLASS_BITS = 3;
+__host__ __device__ inline int tag_class(int32_t tag) { return tag & ((1 << CLASS_BITS) - 1); }
+__host__ __device__ inline int tag_iolet(int32_t tag) { return tag >> CLASS_BITS; }
 enum : int32_t { KIND_INLET = 0, KIND_OUTLET = 1 };
 enum : int32_t { WALL_SBB = 0, WALL_BOUZIDI = 1 };
 enum : int32_t { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1 };
 enum : int32_t { PREC_F64 = 0, PREC_F32 = 1, PREC_F16 = 2, PREC_F16W = 3, PREC_F16SR = 4 };
 
 // One work-group's share of sites: a contiguous internal range inside one
-// domain and one class.  tag = class | (global iolet id << 2).
+// domain and one class.  tag = class | (global iolet id << CLASS_BITS).
 struct Entry {
     int32_t start;
     int32_t count;
@@ -83,7 +87,7 @@ struct KArgs {
     int64_t Npad;            // N rounded up to whole tiles (lattice extent)
     void *lat0, *lat1;
     const int32_t *src;
-    const int16_t *d16;      // [18][N] upstream site minus s for K_NEAR sites
+    const int16_t *d16;      // [18][N] upstream site minus s for K_NEAR / K_NEARWALL sites
     const float *bq;
     const double *bphi;
     void *up0, *up1;

@@ -153,6 +153,23 @@ __device__ __forceinline__ void pull_indices(const KArgs &a, int klass, int64_t 
     }
 }
 
+// Pull indices of a boundary site (-1 for a wall link, -2-g for iolet g): from
+// the int16 delta table for a K_NEARWALL work-group (INT16_MIN marks a wall
+// link), else from the int32 table.
+__device__ __forceinline__ void boundary_indices(const KArgs &a, int klass, int64_t s, int32_t (&sr)[Q]) {
+    const int64_t N = a.N;
+    if (klass == K_NEARWALL) {
+#pragma unroll
+        for (int j = 1; j < Q; ++j) {
+            const int d = a.d16[(size_t)(j - 1) * N + s];
+            sr[j] = (d == -32768) ? -1 : (int32_t)s + d;
+        }
+    } else {
+#pragma unroll
+        for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ const T *lat_ptr(const KArgs &a, int64_t parity) {
     return (const T *)((parity & 1) ? a.lat1 : a.lat0);
@@ -188,14 +205,11 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     const T *__restrict__ lin = lat_ptr<T>(a, p);
-    const int64_t N = a.N;
     int32_t sr[Q];
-    if (BND) {
-#pragma unroll
-        for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
-    } else {
-        pull_indices(a, e.tag & 3, s, sr);
-    }
+    if (BND)
+        boundary_indices(a, tag_class(e.tag), s, sr);
+    else
+        pull_indices(a, tag_class(e.tag), s, sr);
     x[0] = ldc(lin + lidx(0, s), 0);
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
@@ -207,12 +221,12 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
     if (!BND) return;
 
     const int64_t b = s - a.NB;
-    const int klass = e.tag & 3;
+    const int klass = tag_class(e.tag);
     int kind = KIND_INLET;
     R U = 0, nx = 0, ny = 0, nz = 0, phi = 0;
     R rho_out = 0, drho_out = 0, ux = 0, uy = 0, uz = 0;
     if (klass == K_IOLET) {
-        const int g = e.tag >> 2;
+        const int g = tag_iolet(e.tag);
         const IoletDev &io = a.io[g];
         kind = io.kind;
         const double v = a.bc[(p & 1) * a.n_io + g];
@@ -459,7 +473,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
     const int64_t tn = (MODE == M_RAW) ? t : t + 1;
     const int eidx = a.e_off + block_index(a.xcd_remap);
     const Entry e = a.entries[eidx];
-    const int klass = e.tag & 3;
+    const int klass = tag_class(e.tag);
     const SegDev &sg = a.seg[e.seg];
     const int tid = threadIdx.x;
     const bool act = tid < e.count;
@@ -541,7 +555,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
     if (__ballot(bad) != 0 && (tid & 63) == 0) a.ctrl->nan_flag = 1;
 
     if (klass == K_IOLET) {
-        const IoletDev &io = a.io[e.tag >> 2];
+        const IoletDev &io = a.io[tag_iolet(e.tag)];
         double un = 0.0, rh = 0.0;
         if (act) {
             un = (double)ux * io.nrm[0] + (double)uy * io.nrm[1] + (double)uz * io.nrm[2];
@@ -697,14 +711,11 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     const T *__restrict__ A = (const T *)a.lat0;
-    const int64_t N = a.N;
     // the pull table: needed by odd sweeps (gather/scatter) and by boundary sites
-    if (BND) {
-#pragma unroll
-        for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
-    } else if (ODD) {
-        pull_indices(a, e.tag & 3, s, sr);
-    }
+    if (BND)
+        boundary_indices(a, tag_class(e.tag), s, sr);
+    else if (ODD)
+        pull_indices(a, tag_class(e.tag), s, sr);
     if (!ODD) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) x[i] = ldc(A + lidx(i, s), i);
@@ -735,7 +746,7 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
     // Candidate values are computed for every lane and selected, so the
     // divergent link mix of boundary sites costs no branches.
     const int64_t p = t - 1;
-    const int klass = e.tag & 3;
+    const int klass = tag_class(e.tag);
     if (bz) {
         // halfway and q >= 1/2 values were stored final; q < 1/2 needs the
         // second node x_s + c_j, whose population arrived as x[jb] (never
@@ -749,7 +760,7 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
         }
     }
     if (klass == K_IOLET) {
-        const int g = e.tag >> 2;
+        const int g = tag_iolet(e.tag);
         const IoletDev &io = a.io[g];
         const double v = a.bc[(p & 1) * a.n_io + g];
         if (io.kind == KIND_INLET) {
@@ -790,7 +801,7 @@ __device__ __forceinline__ void aa_moments(const KArgs &a, const Entry &e, int e
                                            typename Arith<T>::R Fy, typename Arith<T>::R Fz, double *lds) {
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
-    const int klass = e.tag & 3;
+    const int klass = tag_class(e.tag);
     R rho = 1, ux = 0, uy = 0, uz = 0;
     bool bad = false;
     if (act) {
@@ -817,7 +828,7 @@ __device__ __forceinline__ void aa_moments(const KArgs &a, const Entry &e, int e
     }
     if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) a.ctrl->nan_flag = 1;
     if (klass == K_IOLET) {
-        const IoletDev &io = a.io[e.tag >> 2];
+        const IoletDev &io = a.io[tag_iolet(e.tag)];
         double un = 0.0, rh = 0.0;
         if (act) {
             un = (double)ux * io.nrm[0] + (double)uy * io.nrm[1] + (double)uz * io.nrm[2];
@@ -853,7 +864,7 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     const int direct = a.ctrl->direct;
     const int eidx = a.e_off + block_index(a.xcd_remap);
     const Entry e = a.entries[eidx];
-    const int klass = e.tag & 3;
+    const int klass = tag_class(e.tag);
     const SegDev &sg = a.seg[e.seg];
     const bool act = (int)threadIdx.x < e.count;
     const int64_t s = (int64_t)e.start + threadIdx.x;

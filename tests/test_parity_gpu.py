@@ -332,8 +332,9 @@ def test_xcd_runs_schedule(hl, oracle_mod, order, sched):
     inf = g.info()
     assert inf["n_sites"] > 8 * 64 * 64 + 64 * 10
     if order & 8:
-        # bricked layouts address interior bulk sites through int16 deltas
-        assert 0 < inf["n_near"] < inf["n_bulk"]
+        # bricked layouts address sites whose neighbours share their brick
+        # through int16 deltas
+        assert 0 < inf["n_near"] < inf["n_sites"]
     check64(errors(g, o))
 
 
