@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -52,13 +53,25 @@ def bytes_per_site(prec, aa=False, near=0.0):
     return 2 * 19 * STORE_BYTES[prec] + (9 if aa else 18) * (4.0 - 2.0 * near)
 
 
-def kernel_source_hash():
-    """Hash of the library sources: the kernels, the layout structs they read
-    and the host code that orders the sites and builds the schedule."""
+def _code_only(text):
+    """Source text without comments and blank lines (a comment edit does not
+    change the kernels)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def kernel_source_hash(read=None):
+    """Hash of the library code: the kernels, the layout structs they read and
+    the host code that orders the sites and builds the schedule."""
     h = hashlib.sha256()
     for name in ("hl_kernels.hip", "hl_internal.h", "hl_api.cpp"):
-        with open(os.path.join(ROOT, "paper_2010_04144_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_2010_04144_amd", "csrc", name)) as fh:
+                text = fh.read()
+        else:
+            text = read(name)
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -3,12 +3,15 @@
 // One lane owns one fluid site.  A step t -> t+1 is the fused pull form of
 // the stream-and-collide update (Sec. 2 of the paper: D3Q19, single
 // relaxation time, rigid walls, velocity and pressure boundaries):
-//   1. gather f_j(x, t+1) = f*_j(x - c_j, t) through the int32 pull table,
+//   1. gather f_j(x, t+1) = f*_j(x - c_j, t) through the pull table (int32
+//      indices, or int16 deltas for sites whose neighbours share their brick),
 //   2. replace the populations whose upstream voxel is not fluid by the
 //      boundary rule of that link (halfway or Bouzidi wall, Ladd velocity
 //      inlet, equilibrium pressure outlet),
 //   3. take the moments, relax toward the second-order equilibrium with
 //      Guo's forcing term, and store f*(t+1) to the other lattice.
+// The in-place (AA-pattern) sweeps further below perform the same update on
+// a single lattice.
 // Work-groups whose sites border an iolet also reduce (in FP64, in a fixed
 // order) the mean velocity along the iolet normal and the mean density; a
 // one-work-group kernel queued after them turns those means into the
