@@ -102,3 +102,26 @@ def test_bad_arguments_rejected_before_device(hl):
     assert lib.hl_create(ct.byref(h), 0, 0, hl.HL_ORDER_BRICK_32) == hl.HL_E_INVAL  # needs HL_ORDER_BRICK
     assert lib.hl_create(None, 0, 0, 0) == hl.HL_E_INVAL
     lib.hl_destroy(None)
+
+
+@pytest.mark.slow
+def test_validate_site_list_beyond_2_31_entries():
+    """A periodic box of 113,126,400 sites: its neighbour table holds
+    2,149,401,600 entries (more than 2^31, the paper's BigCount limit of
+    Sec. 2.1), which the host checks walk with 64-bit offsets; a broken
+    reverse link near the end is still found.  About 9 GB of host memory."""
+    import paper_2010_04144_amd as hl
+    nx, ny, nz = 480, 480, 491
+    n = nx * ny * nz
+    assert 19 * n > 2 ** 31
+    cx = [0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0]
+    cy = [0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1]
+    cz = [0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1]
+    nbr = np.empty((19, n), dtype=np.int32)
+    idx = np.arange(n, dtype=np.int32).reshape(nz, ny, nx)
+    for i in range(19):
+        nbr[i] = np.roll(idx, shift=(-cz[i], -cy[i], -cx[i]), axis=(0, 1, 2)).reshape(-1)
+    del idx
+    assert hl.hl_validate_sites(nbr, 0) == hl.HL_OK
+    nbr[18, n - 7] = (nbr[18, n - 7] + 1) % n
+    assert hl.hl_validate_sites(nbr, 0) == hl.HL_E_INVAL
