@@ -1479,7 +1479,17 @@ int hl_autotune(hl_ctx *ctx, int budget_ms) {
     if ((rc = hl_get_state(ctx, nullptr, &bytes)) != HL_OK) return rc;
     std::vector<char> saved(bytes);
     if ((rc = hl_get_state(ctx, saved.data(), &bytes)) != HL_OK) return rc;
-    const int drive = ctx->drive;
+    // the caller's drive comes back and the events go away on every exit
+    struct Guard {
+        hl_ctx *c;
+        int drive;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Guard() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            c->drive = drive;
+        }
+    } guard{ctx, ctx->drive};
     ctx->drive = HL_DRIVE_LAUNCH;
     struct Cand { int block, flags; double ms; };
     std::vector<Cand> cands;
@@ -1489,9 +1499,9 @@ int hl_autotune(hl_ctx *ctx, int budget_ms) {
     for (int b : {64, 128, 256})
         for (int f : {0, R1, RR, F, F | R1, F | RR, P, P | R1, P | RR})
             if (pairs_ok || !(f & HL_SCHED_PAIRS)) cands.push_back({b, f, 0.0});
-    hipEvent_t e0, e1;
-    HIPC(ctx, hipEventCreate(&e0));
-    HIPC(ctx, hipEventCreate(&e1));
+    HIPC(ctx, hipEventCreate(&guard.e0));
+    HIPC(ctx, hipEventCreate(&guard.e1));
+    hipEvent_t e0 = guard.e0, e1 = guard.e1;
     // steps per candidate from one timed step of the current schedule
     int64_t reps = 2;
     {
@@ -1517,11 +1527,9 @@ int hl_autotune(hl_ctx *ctx, int budget_ms) {
         HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
         cd.ms = (double)ms / (double)reps;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     const Cand best = *std::min_element(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
     if ((rc = hl_set_schedule(ctx, best.block, best.flags)) != HL_OK) return rc;
-    ctx->drive = drive;
+    ctx->drive = guard.drive;
     return hl_set_state(ctx, saved.data(), saved.size());
 }
 
