@@ -144,15 +144,17 @@ __device__ __forceinline__ bool bulk_class(int klass) { return klass == K_BULK |
 
 // Pull indices of a bulk site: from the int16 delta table for a K_NEAR work-
 // group (half the index traffic), else from the int32 table.  The class is
-// uniform over the work-group, so the branch does not diverge.
+// uniform over the work-group, so the branch does not diverge.  Index lines
+// are read once per step, so they are loaded non-temporally and leave the L2
+// to the lattice lines that neighbouring gathers reuse.
 __device__ __forceinline__ void pull_indices(const KArgs &a, int klass, int64_t s, int32_t (&sr)[Q]) {
     const int64_t N = a.N;
     if (klass == K_NEAR) {
 #pragma unroll
-        for (int j = 1; j < Q; ++j) sr[j] = (int32_t)s + (int32_t)a.d16[(size_t)(j - 1) * N + s];
+        for (int j = 1; j < Q; ++j) sr[j] = (int32_t)s + (int32_t)__builtin_nontemporal_load(a.d16 + (size_t)(j - 1) * N + s);
     } else {
 #pragma unroll
-        for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+        for (int j = 1; j < Q; ++j) sr[j] = __builtin_nontemporal_load(a.src + (size_t)(j - 1) * N + s);
     }
 }
 
@@ -164,12 +166,12 @@ __device__ __forceinline__ void boundary_indices(const KArgs &a, int klass, int6
     if (klass == K_NEARWALL) {
 #pragma unroll
         for (int j = 1; j < Q; ++j) {
-            const int d = a.d16[(size_t)(j - 1) * N + s];
+            const int d = __builtin_nontemporal_load(a.d16 + (size_t)(j - 1) * N + s);
             sr[j] = (d == -32768) ? -1 : (int32_t)s + d;
         }
     } else {
 #pragma unroll
-        for (int j = 1; j < Q; ++j) sr[j] = a.src[(size_t)(j - 1) * N + s];
+        for (int j = 1; j < Q; ++j) sr[j] = __builtin_nontemporal_load(a.src + (size_t)(j - 1) * N + s);
     }
 }
 
