@@ -18,7 +18,7 @@ _lib = None
 
 INLET, OUTLET = 0, 1
 SBB, BOUZIDI = 0, 1
-ALTERNATE, BOTH = 0, 1
+ALTERNATE, BOTH, VEL = 0, 1, 2   # VEL: velocity-reverse coupling (a bit, combines with BOTH)
 
 _P = ct.c_void_p
 _D = ct.POINTER(ct.c_double)

@@ -21,7 +21,10 @@
  *      phibar = mean inlet profile factor over the inlet's sites, so that the
  *      site mean of the imposed velocity is s times the arterial mean;
  *      reverse: arterial outlet pressure = mean over its veins of
- *      p_vein / (1 - dP/P0), which is Eq. (1) solved for P0)
+ *      p_vein / (1 - dP/P0), which is Eq. (1) solved for P0; in the
+ *      velocity-reverse mode the reverse half instead sets the arterial
+ *      outlet's target mean velocity to the mean over its veins of
+ *      mean_u(vein) / s, imposed as a peak of that value / phibar)
  *   4. LBGK collision with Guo's forcing term (Guo, Zheng & Shi 2002, which
  *      Sec. 3 names for the explicit force):
  *        f*_i = f_i - (f_i - feq_i)/tau
@@ -39,6 +42,8 @@
  *          u_w = U_k(n) max(0, 1 - r^2/R_k^2) n_k, r = distance of x from
  *          the iolet axis
  *        pressure outlet k:        feq_ib(rho_out_k(n), u(x, n))
+ *        coupled arterial outlet in the velocity-reverse mode: the Ladd
+ *          rule above with the outlet's outward normal
  *   6. swap the two arrays.
  *
  * Sums run over directions in index order and over sites in caller order.
@@ -93,14 +98,17 @@ static double series_at(const series_t *s, double t) {
 
 enum { KIND_INLET = 0, KIND_OUTLET = 1 };
 enum { WALL_SBB = 0, WALL_BOUZIDI = 1 };
-enum { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1 };
+/* coupling mode bits: both directions every step; velocity-reverse */
+enum { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1, COUPLE_VEL = 2 };
 
 typedef struct {
     int kind;
     double c[3], nrm[3], R;
     series_t wave;     /* inlet peak velocity U(t) or outlet density rho(t) */
     int coupled;       /* 1 when a coupling pair drives this iolet */
-    double held;       /* held coupled value (U for inlets, rho for outlets) */
+    double held;       /* held coupled value (U for inlets, rho for outlets,
+                          U for outlets in the velocity-reverse mode) */
+    int ladd;          /* 1 when its links take the Ladd velocity rule */
     double bc;         /* value used by the current stream step */
     double phibar;     /* mean profile factor over the bordering sites */
     /* means of the current f */
@@ -315,6 +323,7 @@ int or_couple(or_sys *s, int da, int ka, int db, int kb, double sv, double delta
     return 0;
 }
 
+/* Coupling mode bits (COUPLE_BOTH, COUPLE_VEL); set before or_init. */
 void or_set_coupling_mode(or_sys *s, int mode) { s->mode = mode; }
 
 static void body_force(const domain_t *d, int64_t t, double *F) {
@@ -373,8 +382,8 @@ static void iolet_means(domain_t *d) {
 
 /* Step 3: boundary values for the stream that follows step t. */
 static void boundary_values(or_sys *s) {
-    int fwd = (s->mode == COUPLE_BOTH) || (s->t % 2 == 0);
-    int rev = (s->mode == COUPLE_BOTH) || (s->t % 2 == 1);
+    int fwd = (s->mode & COUPLE_BOTH) || (s->t % 2 == 0);
+    int rev = (s->mode & COUPLE_BOTH) || (s->t % 2 == 1);
     if (fwd) {
         for (int p = 0; p < s->npair; ++p) {
             pair_t *pr = &s->pairs[p];
@@ -396,11 +405,19 @@ static void boundary_values(or_sys *s) {
             for (int q = 0; q < s->npair; ++q) {
                 pair_t *o = &s->pairs[q];
                 if (o->da != pr->da || o->ka != pr->ka) continue;
-                double pv = (s->d[o->db].io[o->kb].mean_rho - RHO0) / 3.0;
-                sum = sum + pv / (1.0 - o->delta);
+                if (s->mode & COUPLE_VEL) {
+                    /* the vein carries s times the artery's mean velocity */
+                    sum = sum + s->d[o->db].io[o->kb].mean_u / o->s;
+                } else {
+                    double pv = (s->d[o->db].io[o->kb].mean_rho - RHO0) / 3.0;
+                    sum = sum + pv / (1.0 - o->delta);
+                }
                 cnt = cnt + 1;
             }
-            out->held = RHO0 + 3.0 * (sum / (double)cnt);
+            if (s->mode & COUPLE_VEL)
+                out->held = out->phibar > 0.0 ? (sum / (double)cnt) / out->phibar : 0.0;
+            else
+                out->held = RHO0 + 3.0 * (sum / (double)cnt);
         }
     }
     for (int k = 0; k < s->ndom; ++k) {
@@ -449,7 +466,7 @@ static void collide_stream(domain_t *d, int64_t t, int nthreads) {
             } else {
                 int k = -2 - y;
                 const iolet_t *io = &d->io[k];
-                if (io->kind == KIND_INLET) {
+                if (io->ladd) {
                     double phi = profile(io, d->coords, n, x);
                     double cu = 0.0;
                     for (int a = 0; a < 3; ++a) cu = cu + C[i][a] * (io->bc * phi * io->nrm[a]);
@@ -493,7 +510,9 @@ int or_init(or_sys *s) {
         }
         for (int j = 0; j < d->n_iolet; ++j) {
             iolet_t *io = &d->io[j];
-            io->held = series_at(&io->wave, 0.0);
+            io->ladd = io->kind == KIND_INLET || (io->coupled && (s->mode & COUPLE_VEL));
+            /* a velocity-driven outlet starts from rest */
+            io->held = (io->ladd && io->kind == KIND_OUTLET) ? 0.0 : series_at(&io->wave, 0.0);
             io->phibar = cnt[j] ? sp[j] / (double)cnt[j] : 0.0;
         }
         free(sp);

@@ -413,3 +413,25 @@ def test_coupled_1to3_reaches_eq2_ratios(oracle_mod, mode):
     expect = 1.0 + 3.0 * np.mean(pb[:3] / (1 - dp))
     assert abs(bc[1] - expect) < 0.02 * abs(expect - 1.0)
     assert pb[:3].min() > 0
+
+
+def test_velocity_reverse_reading_is_unstable(oracle_mod):
+    """Sec. 3 leaves open what the reverse direction sets at an arterial
+    outlet.  Read literally, as a velocity boundary whose mean is the mean over
+    its veins of mean_u(vein) / s, the coupled loop has no pressure feedback:
+    the outlet sites of the filling artery move faster than the imposed mean,
+    the veins hand that back, and the loop gain exceeds one, so the 1:3 tubes
+    leave the low-Mach range within 100 steps.  Reading the pressure back
+    (the rule the library implements) keeps the same system near rest.  At
+    rest both readings hold the equilibrium to round-off."""
+    _, w = oracle_mod.lattice()
+    for mode in (oracle_mod.VEL, oracle_mod.VEL | oracle_mod.BOTH):
+        rest, _, _ = _coupled_1to3(oracle_mod, mode, 40, u_in=0.0)
+        for d in (0, 1):
+            assert np.abs(rest.f(d) - w[:, None]).max() < 5e-16
+    lit, _, _ = _coupled_1to3(oracle_mod, oracle_mod.VEL, 100)
+    _, u_lit = lit.moments(0)
+    assert not (np.abs(u_lit).max() < 0.1)
+    ref, _, _ = _coupled_1to3(oracle_mod, oracle_mod.ALTERNATE, 100)
+    _, u_ref = ref.moments(0)
+    assert np.abs(u_ref).max() < 0.05
