@@ -339,6 +339,18 @@ int hl_get_info(hl_ctx *ctx, hl_info *out);
  * (t advances). */
 int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd);
 
+/* Measured copy ceiling (no context): copy `bytes` bytes from src to dst, two
+ * device buffers of the current device that the caller owns (16-byte aligned,
+ * not overlapping, bytes a positive multiple of 16), with one 16-byte element
+ * per lane and non-temporal loads and stores; one untimed launch, then reps
+ * (1..1000) launches timed with HIP events on `stream` (NULL: the default
+ * stream).  *gbps = bytes read plus bytes written per second, in GB/s.  It is
+ * the practical HBM bound the step kernels' bandwidth is compared with, next
+ * to the published peak.  dst is overwritten with src.  HL_E_INVAL on a bad
+ * argument, HL_E_RANGE when the copy needs more than 2^31 - 1 work-groups,
+ * HL_E_DEVICE when a HIP call fails. */
+int hl_copy_bandwidth(void *dst, const void *src, int64_t bytes, int32_t reps, void *stream, double *gbps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,6 +42,21 @@ def hl_validate_sites(nbr, n_iolet):
     return lib().hl_validate_sites(n, nbr.ctypes.data_as(ct.POINTER(ct.c_int32)), int(n_iolet))
 
 
+def hl_copy_bandwidth(dst, src, nbytes, reps=20, stream=None):
+    """Measured copy ceiling in GB/s: ``nbytes`` copied from ``src`` to ``dst``
+    (torch tensors or raw device pointers, caller-owned) ``reps`` times on
+    ``stream`` (a torch stream, a raw handle or None)."""
+    d = dst.data_ptr() if hasattr(dst, "data_ptr") else int(dst)
+    s = src.data_ptr() if hasattr(src, "data_ptr") else int(src)
+    st = getattr(stream, "cuda_stream", stream)
+    out = ct.c_double(0.0)
+    rc = lib().hl_copy_bandwidth(ct.c_void_p(d), ct.c_void_p(s), int(nbytes), int(reps),
+                                 ct.c_void_p(st or 0), ct.byref(out))
+    if rc != HL_OK:
+        raise HLError(rc, f"hl_copy_bandwidth failed: {status_string(rc)}")
+    return out.value
+
+
 def _pd(a):
     return a.ctypes.data_as(ct.POINTER(ct.c_double))
 

@@ -117,6 +117,7 @@ SIGNATURES = {
     "hl_set_schedule": (_I, [_P, _I32, _I32]),
     "hl_get_info": (_I, [_P, ct.POINTER(hl_info)]),
     "hl_time_kernels": (_I, [_P, _I64, _pD, _pD]),
+    "hl_copy_bandwidth": (_I, [_P, _P, _I64, _I32, _P, _pD]),
 }
 
 _lib = None

@@ -104,6 +104,28 @@ def test_bad_arguments_rejected_before_device(hl):
     lib.hl_destroy(None)
 
 
+def test_copy_bandwidth_argument_checks(hl):
+    """The copy-ceiling call rejects bad arguments on the host, before any
+    device call (the pointers below are never touched)."""
+    lib = hl.lib()
+    out = ct.c_double(-1.0)
+    P = ct.c_void_p
+    a, b = P(1 << 20), P(1 << 30)
+    assert lib.hl_copy_bandwidth(None, a, 64, 1, None, ct.byref(out)) == hl.HL_E_INVAL
+    assert lib.hl_copy_bandwidth(b, None, 64, 1, None, ct.byref(out)) == hl.HL_E_INVAL
+    assert lib.hl_copy_bandwidth(b, a, 64, 1, None, None) == hl.HL_E_INVAL
+    assert lib.hl_copy_bandwidth(b, a, 0, 1, None, ct.byref(out)) == hl.HL_E_INVAL
+    assert lib.hl_copy_bandwidth(b, a, 40, 1, None, ct.byref(out)) == hl.HL_E_INVAL      # not whole 16-byte units
+    assert lib.hl_copy_bandwidth(b, a, 64, 0, None, ct.byref(out)) == hl.HL_E_INVAL
+    assert lib.hl_copy_bandwidth(b, a, 64, 1001, None, ct.byref(out)) == hl.HL_E_INVAL
+    assert lib.hl_copy_bandwidth(P((1 << 30) + 8), a, 64, 1, None, ct.byref(out)) == hl.HL_E_INVAL  # misaligned
+    assert lib.hl_copy_bandwidth(P((1 << 20) + 16), a, 64, 1, None, ct.byref(out)) == hl.HL_E_INVAL  # overlap
+    assert lib.hl_copy_bandwidth(a, P((1 << 20) + 48), 64, 1, None, ct.byref(out)) == hl.HL_E_INVAL  # overlap
+    # 2^44 bytes need 2^32 work-groups of 256 lanes: beyond the grid limit
+    assert lib.hl_copy_bandwidth(P(1 << 52), a, 1 << 44, 1, None, ct.byref(out)) == hl.HL_E_RANGE
+    assert out.value == -1.0
+
+
 @pytest.mark.slow
 def test_validate_site_list_beyond_2_31_entries():
     """A periodic box of 113,126,400 sites: its neighbour table holds

@@ -529,3 +529,23 @@ def test_stochastic_fp16_store_is_unbiased(hl, order):
                 m = off[i].mean()
                 print("sr", i, v[i], m, (m - v[i]) / max(sd, 1e-30), flush=True)
                 assert abs(m - v[i]) <= 5 * sd + 1e-15, (i, v[i], m, sd)
+
+
+def test_copy_bandwidth_ceiling(hl):
+    """The copy-ceiling call copies its source exactly (odd element count,
+    so the last work-group is partial) and reports a positive bandwidth; a
+    second call on a smaller size overwrites only that prefix."""
+    import torch
+    gen = torch.Generator(device="cuda").manual_seed(20100414)
+    n = (64 << 20) + 16 * 37
+    src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=gen)
+    dst = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    gbps = hl.hl_copy_bandwidth(dst, src, n, reps=3, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert gbps > 0.0
+    assert torch.equal(dst, src)
+    dst.zero_()
+    hl.hl_copy_bandwidth(dst, src, 4096, reps=1)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:4096], src[:4096])
+    assert int(dst[4096:].count_nonzero()) == 0
