@@ -151,6 +151,43 @@ def test_mass_conserved_in_closed_domains(oracle_mod):
             assert np.abs(u[2]).max() > 1e-3
 
 
+def test_open_domain_mass_budget(oracle_mod):
+    """Open pipe (velocity inlet, pressure outlet away from rho0, Bouzidi
+    walls off so the walls conserve mass exactly): the mass change of one
+    step equals what the iolet links add, link by link: minus 6 w_i rho0
+    (c_i . u_w) for an inlet link (Ladd), feq_ib(rho_out, u(x)) - f*_i(x) for
+    an outlet link.  The collision and the bounce-back walls add nothing."""
+    geo = synth.cylinder(nz=16)
+    s = _system(oracle_mod, geo, tau=0.7, u_in=0.02, rho_out=1.002)
+    s.step(25)
+    c, w = oracle_mod.lattice()
+    nbr = geo.nbr
+    n = nbr.shape[1]
+    m0 = _neumaier(s.f().ravel())
+    _, u = s.moments()
+    s.step(1)
+    m1 = _neumaier(s.f().ravel())
+    fs = s.fpost()
+    bc = s.last_bc()
+    terms = []
+    for i in range(1, 19):
+        ib = i + 1 if i % 2 else i - 1
+        for x in np.flatnonzero(nbr[i] <= -2):
+            k = -2 - int(nbr[i, x])
+            io = geo.iolets[k]
+            if io.kind == "inlet":
+                d = geo.coords[:, x] - np.asarray(io.centre, float)
+                nrm = np.asarray(io.normal, float)
+                r2 = d @ d - (d @ nrm) ** 2
+                phi = max(0.0, 1.0 - r2 / io.radius ** 2)
+                terms.append(-6.0 * w[i] * 1.0 * (c[i] @ nrm) * bc[k] * phi)
+            else:
+                terms.append(oracle_mod.feq(bc[k], u[:, x])[ib] - fs[i, x])
+    budget = _neumaier(terms)
+    assert abs(budget) > 1e-4                      # the iolets do move mass
+    assert abs((m1 - m0) - budget) < 1e-13 * n
+
+
 def _dense_reference(solid, F, tau, steps):
     """Dense lattice on a periodic box with np.roll streaming and halfway
     bounce-back at solid cells.  Written here independently of the oracle."""
