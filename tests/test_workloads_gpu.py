@@ -1,4 +1,5 @@
-"""The other workload configurations on the GPU: the full-size Womersley pipe
+"""The workload configurations on the GPU: the branching artery at full size
+in the layouts and schedule the benchmark times, the full-size Womersley pipe
 against the analytic solution, and reduced-size twins of the coupled
 arterial-venous pair and of the uneven ensemble against the FP64 oracle."""
 import os
@@ -7,10 +8,11 @@ import numpy as np
 import pytest
 
 import synth
-from scenarios import build_gpu, build_oracle, errors, from_workload
+from scenarios import Dom, Scenario, build_gpu, build_oracle, errors, from_workload
 
 pytestmark = pytest.mark.gpu
 THREADS = min(8, os.cpu_count() or 1)
+TOL64 = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -21,6 +23,38 @@ def hl():
     import paper_2010_04144_amd as hl
     hl.lib()
     return hl
+
+
+def test_branching_artery_full_size(hl, oracle_mod):
+    """The benchmark workload at full size (Murray tree of depth 8, root radius
+    40, 768^3 box, 6,064,894 sites, Bouzidi walls, tau 0.55, steady inlet) in
+    the configurations the benchmark times: 32^3 bricks with the fused XCD-runs
+    schedule, two lattices in FP64 and FP32 offset storage and in place in
+    FP16 offset storage, each against the FP64 oracle after five steps (an odd
+    count, so the in-place run ends on an odd sweep).  Every output is
+    compared, not a sample: the oracle takes about a second per step here."""
+    geo = synth.murray_tree_c2(box=768)
+    assert geo.n == 6064894
+    sc = Scenario([Dom(geo, tau=0.55, bouzidi=True, inlets={0: (0.01, (), (), 1.0)})])
+    o = build_oracle(sc, oracle_mod)
+    o.step(5, min(16, os.cpu_count() or 1))
+    sched = hl.HL_SCHED_FUSED | hl.HL_SCHED_XCD_REMAP | hl.HL_SCHED_XCD_RUNS
+    bricks = hl.HL_ORDER_BRICK | hl.HL_ORDER_BRICK_32
+    for prec, order, bound in (("f64", bricks, TOL64), ("f32", bricks, 1e-3),
+                               ("f16", bricks | hl.HL_SCHEME_AA, 2e-2)):
+        print(f"branching artery full size: {prec} layout {order}", flush=True)
+        g = build_gpu(sc, hl, prec, order=order)
+        g.commit()
+        g.set_schedule(256, sched)
+        g.step(5)
+        full = prec == "f64"
+        err = errors(g, o, 0, with_f=full, with_wss=full)
+        g.close()
+        print(f"branching artery full size {prec}: {err}", flush=True)
+        if full:
+            assert max(err.values()) <= bound, err
+        else:
+            assert err["e_u"] < bound and err["e_iolet_u"] < bound, err
 
 
 def womersley_error(ctx, wl, phases=8):
@@ -134,7 +168,6 @@ def test_coupled_13_to_1(hl, oracle_mod, order):
     pairs = coupling.build_pairs(0, outlets, oc, aa[1:5], 1, inlets, pos, av[:52], rng.uniform(0.3, 0.7, 52))
     counts = [sum(1 for p in pairs if p[1] == i) for i in outlets]
     assert counts == [13, 13, 13, 13], counts
-    from scenarios import Dom, Scenario
     sc = Scenario([Dom(art, tau=0.8, bouzidi=True, inlets={0: (0.02, (), (), 1.0)}),
                    Dom(ven, tau=0.8)], pairs=pairs, mode=0)
     o = build_oracle(sc, oracle_mod)
