@@ -49,6 +49,22 @@ def test_validate_accepts_generated_geometries(hl):
         assert hl.hl_validate_sites(g.nbr, len(g.iolets)) == hl.HL_OK
 
 
+def test_branching_artery_recipe(hl):
+    """The benchmark workload: a seeded Murray tree of depth 8 and root radius
+    40 in a 768^3 box, with the segment length fitted so the tree fits
+    (lambda = 3.7114), gives 6,064,894 sites, one root inlet and 256 leaf
+    outlets, and 4,716,345 wall links, each with a wall fraction in (0, 1];
+    its site list passes the library's host checks."""
+    geo = synth.murray_tree_c2(box=768)
+    assert geo.n == 6064894
+    assert abs(geo.meta["lam"] - 3.7114) < 1e-4
+    kinds = [io.kind for io in geo.iolets]
+    assert kinds[0] == "inlet" and kinds.count("outlet") == 256 and len(kinds) == 257
+    assert int(np.count_nonzero(geo.nbr == -1)) == 4716345 == geo.q.size
+    assert float(geo.q.min()) > 0.0 and float(geo.q.max()) <= 1.0
+    assert hl.hl_validate_sites(geo.nbr, len(geo.iolets)) == hl.HL_OK
+
+
 def test_validate_rejects_malformed_lists(hl):
     g = synth.cylinder(nz=6)
     n = g.n
