@@ -1,0 +1,57 @@
+"""Host logic of the benchmark script, on the CPU: the algorithmic byte
+count per site, the lookup of the committed counter traffic (taken only when
+the kernel sources are the profiled ones), and the refusal of more than one
+GPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    import bench
+    return bench
+
+
+def test_bytes_per_site(bench):
+    # two lattices: 19 populations read and written, 18 int32 pull indices
+    assert bench.bytes_per_site("f64") == 2 * 19 * 8 + 18 * 4 == 376
+    assert bench.bytes_per_site("f32") == 224
+    assert bench.bytes_per_site("f16") == 148
+    # in place: half the index reads on average over an even and an odd sweep
+    assert bench.bytes_per_site("f16", aa=True) == 2 * 19 * 2 + 9 * 4 == 112
+    # int16 deltas halve the index bytes of the near fraction
+    assert bench.bytes_per_site("f32", near=1.0) == 2 * 19 * 4 + 18 * 2
+    assert bench.bytes_per_site("f32", near=0.8119) == pytest.approx(152 + 18 * (0.8119 * 2 + 0.1881 * 4))
+    assert bench.bytes_per_site("f16sr", aa=True, near=0.5) == 76 + 9 * 3
+
+
+def test_source_hash_ignores_comments_only(bench):
+    def reader(extra):
+        def read(name):
+            with open(os.path.join(ROOT, "paper_2010_04144_amd", "csrc", name)) as fh:
+                return fh.read() + extra
+        return read
+    base = bench.kernel_source_hash()
+    assert bench.kernel_source_hash(reader("\n// a note\n/* block\n note */\n\n")) == base
+    assert bench.kernel_source_hash(reader("\nstatic int unused_marker;\n")) != base
+
+
+def test_traffic_lookup(bench, monkeypatch):
+    # the committed counter summary matches the sources as they are
+    assert bench.traffic_from_profile("f32", 40, 256, 11) is not None
+    assert bench.traffic_from_profile("f32", 40, 256, 12345) is None
+    # a kernel change voids it
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda read=None: "0000000000000000")
+    assert bench.traffic_from_profile("f32", 40, 256, 11) is None
+
+
+def test_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
