@@ -400,7 +400,7 @@ def main():
         run_multi(hl, torch, args)
         return
     t0 = time.perf_counter()
-    geo = synth.murray_tree_c2(box=args.box)
+    geo = synth.branching_artery(box=args.box)
     log(f"geometry: {geo.n} sites, fill {geo.meta['fill']:.4f}, lambda {geo.meta['lam']:.3f}, "
         f"{len(geo.iolets)} iolets, {geo.q.size} wall links ({time.perf_counter() - t0:.1f} s)")
 

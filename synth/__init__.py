@@ -2,5 +2,5 @@
 geometry only, none of the lattice Boltzmann arithmetic."""
 from .geometry import (DIRS, INLET, NDIR, OUTLET, WALL, Geometry, Iolet, box, tubes,  # noqa: F401
                        build_site_list, channel, cylinder, iolet_code)
-from .trees import coupled_pair, ensemble, murray_tree_c2, tree_geometry  # noqa: F401
+from .trees import coupled_pair, ensemble, branching_artery, tree_geometry  # noqa: F401
 from . import workloads  # noqa: F401

@@ -175,7 +175,7 @@ def tree_geometry(depth, r0, seed, lam=None, box=None, margin=4, radius_scale=1.
     return g
 
 
-def murray_tree_c2(box=768, depth=8, r0=40.0, seed=20100414 + 2):
+def branching_artery(box=768, depth=8, r0=40.0, seed=20100414 + 2):
     """Branching artery of depth 8, root radius 40, seeded, in a box^3 grid,
     with random Bouzidi wall fractions."""
     return tree_geometry(depth, r0, seed, box=box)

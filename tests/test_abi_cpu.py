@@ -55,7 +55,7 @@ def test_branching_artery_recipe(hl):
     (lambda = 3.7114), gives 6,064,894 sites, one root inlet and 256 leaf
     outlets, and 4,716,345 wall links, each with a wall fraction in (0, 1];
     its site list passes the library's host checks."""
-    geo = synth.murray_tree_c2(box=768)
+    geo = synth.branching_artery(box=768)
     assert geo.n == 6064894
     assert abs(geo.meta["lam"] - 3.7114) < 1e-4
     kinds = [io.kind for io in geo.iolets]

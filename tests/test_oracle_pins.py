@@ -322,19 +322,19 @@ def test_bouzidi_second_order_vs_bounce_back_first_order(oracle_mod):
 
 
 @pytest.fixture(scope="module")
-def c1_steady(oracle_mod):
+def cylinder_steady(oracle_mod):
     geo = synth.cylinder()
     s = _system(oracle_mod, geo, tau=0.8, u_in=0.01)
     s.step(1000)
     return geo, s
 
 
-def test_hagen_poiseuille_c1(c1_steady):
+def test_hagen_poiseuille_cylinder(cylinder_steady):
     """Cylinder, velocity inlet, pressure outlet, 1000 steps: the mid-length
     profile is the parabola within the staircase error, the axial pressure
     gradient matches G = 4 nu u_max / R^2, the outlet holds rho_out and the
     flux is the same at inlet, middle and outlet."""
-    geo, s = c1_steady
+    geo, s = cylinder_steady
     rho, u = s.moments()
     x, y, z = geo.coords
     r2 = (x - 9.5) ** 2 + (y - 9.5) ** 2

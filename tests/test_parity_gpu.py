@@ -33,7 +33,7 @@ def run_both(sc, hl, oracle_mod, steps, precision="f64", gpu_steps_chunks=None):
     return g, o
 
 
-def c1_scenario(q="half", bouzidi=False, nz=64):
+def cylinder_scenario(q="half", bouzidi=False, nz=64):
     geo = synth.cylinder(nz=nz, q=q, seed=3)
     return Scenario([Dom(geo, tau=0.8, bouzidi=bouzidi, inlets={0: (0.01, (), (), 1.0)},
                          outlets={1: (1.0, (), (), 1.0)})])
@@ -44,18 +44,18 @@ def check64(err, tol=TOL64):
     assert not bad, (bad, err)
 
 
-def test_c1_cylinder_fp64_1000_steps(hl, oracle_mod):
+def test_cylinder_fp64_1000_steps(hl, oracle_mod):
     """The plain method on the straight cylinder: SBB walls, parabolic
     velocity inlet, pressure outlet, tau 0.8, 1000 steps."""
-    g, o = run_both(c1_scenario(), hl, oracle_mod, 1000)
+    g, o = run_both(cylinder_scenario(), hl, oracle_mod, 1000)
     err = errors(g, o)
-    print("C1 fp64", err, flush=True)
+    print("cylinder fp64", err, flush=True)
     check64(err)
     assert g.t == 1000 == o.t
 
 
-def test_c1_bouzidi_fp64(hl, oracle_mod):
-    g, o = run_both(c1_scenario(q="cylinder", bouzidi=True), hl, oracle_mod, 400)
+def test_cylinder_bouzidi_fp64(hl, oracle_mod):
+    g, o = run_both(cylinder_scenario(q="cylinder", bouzidi=True), hl, oracle_mod, 400)
     check64(errors(g, o))
 
 
@@ -116,9 +116,9 @@ def test_offset_storage_errors(hl, oracle_mod, prec, bound_u, bound_rho):
     """FP32 / FP16 storage of f - w rho0 with FP32 arithmetic on the cylinder
     after 1000 steps: the errors against the FP64 oracle are reported and
     bounded."""
-    g, o = run_both(c1_scenario(), hl, oracle_mod, 1000, precision=prec)
+    g, o = run_both(cylinder_scenario(), hl, oracle_mod, 1000, precision=prec)
     err = errors(g, o, with_f=True, with_wss=True)
-    print(prec, "C1 errors vs oracle", err, flush=True)
+    print(prec, "cylinder errors vs oracle", err, flush=True)
     assert err["e_u"] < bound_u and err["e_rho"] < bound_rho
 
 
@@ -137,7 +137,7 @@ def test_rest_state_stays_exact(hl):
 def test_graph_and_launch_drivers_are_bitwise_equal(hl):
     res = []
     for drive, spg in ((hl.HL_DRIVE_LAUNCH, 1), (hl.HL_DRIVE_GRAPH, 7)):
-        g = build_gpu(c1_scenario(nz=16), hl)
+        g = build_gpu(cylinder_scenario(nz=16), hl)
         g.set_drive(drive, spg)
         g.step(45)
         res.append(g.populations(0))
@@ -146,13 +146,13 @@ def test_graph_and_launch_drivers_are_bitwise_equal(hl):
 
 def test_checkpoint_resume_bitwise(hl):
     for prec in ("f64", "f32", "f16", "f16w", "f16sr"):
-        a = build_gpu(c1_scenario(nz=16), hl, prec)
+        a = build_gpu(cylinder_scenario(nz=16), hl, prec)
         a.step(60)
         ref = a.populations(0)
-        b = build_gpu(c1_scenario(nz=16), hl, prec)
+        b = build_gpu(cylinder_scenario(nz=16), hl, prec)
         b.step(30)
         blob = b.get_state()
-        c = build_gpu(c1_scenario(nz=16), hl, prec)
+        c = build_gpu(cylinder_scenario(nz=16), hl, prec)
         c.commit()
         c.set_state(blob)
         assert c.t == 30
@@ -161,10 +161,10 @@ def test_checkpoint_resume_bitwise(hl):
 
 
 def test_set_populations_round_trip_is_bitwise(hl):
-    a = build_gpu(c1_scenario(nz=16), hl)
+    a = build_gpu(cylinder_scenario(nz=16), hl)
     a.step(50)
     ref = a.populations(0)
-    b = build_gpu(c1_scenario(nz=16), hl)
+    b = build_gpu(cylinder_scenario(nz=16), hl)
     b.step(20)
     f20 = b.populations(0)
     b.set_populations(0, f20)
@@ -175,7 +175,7 @@ def test_set_populations_round_trip_is_bitwise(hl):
 
 def test_set_populations_matches_oracle(hl, oracle_mod):
     """Load a perturbed state into both and step on."""
-    sc = c1_scenario(nz=16)
+    sc = cylinder_scenario(nz=16)
     o = build_oracle(sc, oracle_mod)
     g = build_gpu(sc, hl)
     rng = np.random.default_rng(9)
@@ -189,7 +189,7 @@ def test_set_populations_matches_oracle(hl, oracle_mod):
 
 
 def test_nan_is_reported_as_divergence(hl):
-    g = build_gpu(c1_scenario(nz=8), hl)
+    g = build_gpu(cylinder_scenario(nz=8), hl)
     g.step(3)
     f = g.populations(0)
     f[4, 17] = np.nan
@@ -202,7 +202,7 @@ def test_nan_is_reported_as_divergence(hl):
 
 @pytest.mark.parametrize("block,flags", [(64, 0), (128, 1), (256, 1), (64, 4), (256, 4)])
 def test_schedules_agree(hl, oracle_mod, block, flags):
-    sc = c1_scenario(nz=24)
+    sc = cylinder_scenario(nz=24)
     o = build_oracle(sc, oracle_mod)
     g = build_gpu(sc, hl)
     g.set_schedule(block, flags)
@@ -240,7 +240,7 @@ def test_nothing_loaded_is_a_state_error(hl):
 
 
 def test_argument_errors(hl):
-    g = build_gpu(c1_scenario(nz=8), hl)
+    g = build_gpu(cylinder_scenario(nz=8), hl)
     with pytest.raises(hl.HLError) as ei:
         g.set_tau(0, 0.5)
     assert ei.value.code == hl.HL_E_INVAL
@@ -263,7 +263,7 @@ def test_argument_errors(hl):
 
 def test_device_reads_match_host_reads(hl):
     import torch
-    g = build_gpu(c1_scenario(nz=16), hl)
+    g = build_gpu(cylinder_scenario(nz=16), hl)
     g.step(40)
     n = g.n[0]
     rho = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -280,7 +280,7 @@ def test_device_reads_match_host_reads(hl):
 
 
 def test_autotune_keeps_state(hl):
-    a = build_gpu(c1_scenario(nz=24), hl)
+    a = build_gpu(cylinder_scenario(nz=24), hl)
     a.step(10)
     before = a.populations(0)
     a.autotune(50)
@@ -379,12 +379,12 @@ def test_aa_tree_bouzidi(hl, oracle_mod, order, sched):
 
 
 def test_aa_cylinder_sbb_1000_steps(hl, oracle_mod):
-    g, o = run_both_order(c1_scenario(), hl, oracle_mod, 1000, AA)
+    g, o = run_both_order(cylinder_scenario(), hl, oracle_mod, 1000, AA)
     check64(errors(g, o))
 
 
 def test_aa_cylinder_exact_q_bouzidi(hl, oracle_mod):
-    g, o = run_both_order(c1_scenario(q="cylinder", bouzidi=True), hl, oracle_mod, 333, AA)
+    g, o = run_both_order(cylinder_scenario(q="cylinder", bouzidi=True), hl, oracle_mod, 333, AA)
     check64(errors(g, o))
 
 
@@ -431,26 +431,26 @@ def test_aa_checkpoint_graph_and_reload(hl, prec):
     """In-place scheme: graph replay equals plain launches bit for bit from an
     odd start, checkpoints resume bit for bit, and reloading the populations
     at an odd step continues exactly (FP64: bitwise)."""
-    ref = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+    ref = build_gpu(cylinder_scenario(nz=16), hl, prec, order=AA)
     ref.set_drive(hl.HL_DRIVE_LAUNCH)
     ref.step(3)
     ref.step(40)
     fa = ref.populations(0)
-    g = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+    g = build_gpu(cylinder_scenario(nz=16), hl, prec, order=AA)
     g.set_drive(hl.HL_DRIVE_GRAPH, 8)
     g.step(3)
     g.step(40)
     assert np.array_equal(g.populations(0), fa)
-    b = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+    b = build_gpu(cylinder_scenario(nz=16), hl, prec, order=AA)
     b.step(21)
     blob = b.get_state()
-    c = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+    c = build_gpu(cylinder_scenario(nz=16), hl, prec, order=AA)
     c.commit()
     c.set_state(blob)
     c.step(22)
     assert np.array_equal(c.populations(0), fa)
     if prec == "f64":
-        d = build_gpu(c1_scenario(nz=16), hl, prec, order=AA)
+        d = build_gpu(cylinder_scenario(nz=16), hl, prec, order=AA)
         d.step(21)
         f21 = d.populations(0)
         d.set_populations(0, f21)
@@ -461,7 +461,7 @@ def test_aa_checkpoint_graph_and_reload(hl, prec):
 
 def test_aa_offset_storage_errors(hl, oracle_mod):
     for prec, bound in (("f32", 2e-4), ("f16", 0.05), ("f16w", 0.05), ("f16sr", 0.05)):
-        sc = c1_scenario()
+        sc = cylinder_scenario()
         o = build_oracle(sc, oracle_mod)
         g = build_gpu(sc, hl, prec, order=AA)
         o.step(1000)
@@ -488,7 +488,7 @@ def test_scaled_fp16_slow_flow(hl, oracle_mod, order):
         g = build_gpu(sc, hl, prec, order=order)
         g.step(1500)
         res[prec] = errors(g, o, with_wss=True)
-        print("slow C1", prec, "order", order, res[prec], flush=True)
+        print("slow cylinder", prec, "order", order, res[prec], flush=True)
         g.close()
     assert res["f16w"]["e_u"] <= res["f16"]["e_u"]
     assert res["f16w"]["e_u"] < 0.05

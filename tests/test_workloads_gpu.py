@@ -33,7 +33,7 @@ def test_branching_artery_full_size(hl, oracle_mod):
     FP16 offset storage, each against the FP64 oracle after five steps (an odd
     count, so the in-place run ends on an odd sweep).  Every output is
     compared, not a sample: the oracle takes about a second per step here."""
-    geo = synth.murray_tree_c2(box=768)
+    geo = synth.branching_artery(box=768)
     assert geo.n == 6064894
     sc = Scenario([Dom(geo, tau=0.55, bouzidi=True, inlets={0: (0.01, (), (), 1.0)})])
     o = build_oracle(sc, oracle_mod)
