@@ -332,8 +332,11 @@ def cylinder_steady(oracle_mod):
 def test_hagen_poiseuille_cylinder(cylinder_steady):
     """Cylinder, velocity inlet, pressure outlet, 1000 steps: the mid-length
     profile is the parabola within the staircase error, the axial pressure
-    gradient matches G = 4 nu u_max / R^2, the outlet holds rho_out and the
-    flux is the same at inlet, middle and outlet."""
+    gradient matches G = 4 nu u_max / R^2, the outlet holds rho_out, the
+    flux is the same at inlet, middle and outlet, and the wall shear stress at
+    each mid-length wall site follows the Poiseuille stress rho nu 2 u_max r /
+    R^2 at its radius r (the staircase normals scatter single sites by up to
+    25 %)."""
     geo, s = cylinder_steady
     rho, u = s.moments()
     x, y, z = geo.coords
@@ -353,6 +356,11 @@ def test_hagen_poiseuille_cylinder(cylinder_steady):
     flux = [u[2, z == k].mean() for k in (0, 32, 63)]
     assert np.ptp(flux) / np.mean(flux) < 0.03
     assert area.tolist() == [208, 208]
+    wall = (geo.nbr[1:] == -1).any(axis=0) & mid
+    ratio = s.wss()[wall] / (rho[wall] * 0.1 * 2 * umax * np.sqrt(r2[wall]) / R2)
+    assert wall.sum() == 60
+    assert abs(ratio.mean() - 1.0) < 0.1
+    assert 0.6 < ratio.min() and ratio.max() < 1.4
 
 
 def test_womersley_pipe(oracle_mod):
