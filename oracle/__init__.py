@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liblbgk_oracle.so")
+# ORACLE_LIB_OVERRIDE names another build of lbgk_oracle.c to load instead (the
+# mutation check of the pins builds deliberately broken copies on the CPU)
+_LIB_PATH = os.environ.get("ORACLE_LIB_OVERRIDE") or os.path.join(_HERE, "liblbgk_oracle.so")
 _lib = None
 
 INLET, OUTLET = 0, 1
@@ -31,6 +33,8 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
+        if os.environ.get("ORACLE_LIB_OVERRIDE"):
+            raise FileNotFoundError(_LIB_PATH)
         from . import build as _b
         _b.build()
     lib = ct.CDLL(_LIB_PATH)

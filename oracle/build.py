@@ -12,14 +12,18 @@ SRC = os.path.join(HERE, "lbgk_oracle.c")
 LIB = os.path.join(HERE, "liblbgk_oracle.so")
 
 
-def build(verbose=False):
-    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-fopenmp", "-Wall", "-o", LIB + ".tmp", SRC, "-lm"]
+FLAGS = ["-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+         "-fopenmp", "-Wall"]
+
+
+def build(verbose=False, src=SRC, out=LIB, extra=()):
+    """Compile `src` (the oracle source, or a copy of it) into `out`."""
+    cmd = ["gcc", *FLAGS, *extra, "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

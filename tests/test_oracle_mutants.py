@@ -1,0 +1,147 @@
+"""Mutation check of the oracle pins.
+
+Each mutant plants one plausible slip (a swapped branch operand, a dropped
+factor, a wrong sign or index) in a copy of the oracle's C source, builds it
+on the CPU in a temporary folder, and runs the pins named beside it against
+that copy in a child process (ORACLE_LIB_OVERRIDE): every named pin must
+fail.  The unmodified source, built the same way, passes them all.  This is
+what shows that the pins fix the oracle rather than restate it.
+"""
+import os
+import re
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lbgk_oracle.c")
+PINS = "tests/test_oracle_pins.py"
+
+# (name, text in the oracle source, replacement, pins that must fail)
+MUTANTS = [
+    ("bouzidi far branch: own populations swapped",
+     "v = fsi / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * d->fs[(size_t)ib * n + x];",
+     "v = d->fs[(size_t)ib * n + x] / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * fsi;",
+     ["test_bouzidi_at_half_is_bounce_back", "test_bouzidi_far_wall_second_order"]),
+    ("bouzidi near branch: weights swapped",
+     "if (back >= 0) v = 2.0 * q * fsi + (1.0 - 2.0 * q) * d->fs[(size_t)i * n + back];",
+     "if (back >= 0) v = (1.0 - 2.0 * q) * fsi + 2.0 * q * d->fs[(size_t)i * n + back];",
+     ["test_bouzidi_second_order_vs_bounce_back_first_order"]),
+    ("bouzidi near branch: wrong fallback without a second node",
+     "if (back >= 0) v = 2.0 * q * fsi + (1.0 - 2.0 * q) * d->fs[(size_t)i * n + back];",
+     "if (back >= 0) v = 2.0 * q * fsi + (1.0 - 2.0 * q) * d->fs[(size_t)i * n + back];"
+     " else v = d->fs[(size_t)ib * n + x];",
+     ["test_bouzidi_without_second_node_is_bounce_back"]),
+    ("series: 2 pi dropped",
+     "double ph = 2.0 * M_PI * (double)m * t / s->period;",
+     "double ph = (double)m * t / s->period;",
+     ["test_waveform_series_period_mean_and_harmonics"]),
+    ("series: harmonic number dropped",
+     "double ph = 2.0 * M_PI * (double)m * t / s->period;",
+     "double ph = 2.0 * M_PI * t / s->period;",
+     ["test_waveform_series_period_mean_and_harmonics"]),
+    ("series: cosine and sine coefficients swapped",
+     "v = v + s->a[m - 1] * cos(ph) + s->b[m - 1] * sin(ph);",
+     "v = v + s->a[m - 1] * sin(ph) + s->b[m - 1] * cos(ph);",
+     ["test_waveform_series_period_mean_and_harmonics"]),
+    ("equilibrium: second-order coefficient",
+     "feq[i] = W[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);",
+     "feq[i] = W[i] * rho * (1.0 + 3.0 * cu + 4.0 * cu * cu - 1.5 * uu);",
+     ["test_feq_moments", "test_sparse_addressing_matches_dense_bruteforce"]),
+    ("Guo source: sign of u",
+     "s = s + (3.0 * (C[i][a] - u[a]) + 9.0 * cu * C[i][a]) * F[a];",
+     "s = s + (3.0 * (C[i][a] + u[a]) + 9.0 * cu * C[i][a]) * F[a];",
+     ["test_collision_conserves_and_relaxes", "test_sparse_addressing_matches_dense_bruteforce"]),
+    ("moments: half-force shift dropped",
+     "for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * F[a]) / r;",
+     "for (int a = 0; a < 3; ++a) u[a] = j[a] / r;",
+     ["test_sparse_addressing_matches_dense_bruteforce", "test_plane_poiseuille_exact_at_magic_tau"]),
+    ("streaming: pushed into the opposite direction",
+     "d->fn[(size_t)i * n + y] = fsi;",
+     "d->fn[(size_t)ib * n + y] = fsi;",
+     ["test_sparse_addressing_matches_dense_bruteforce"]),
+    ("inlet: sign of the Ladd term",
+     "d->fn[(size_t)ib * n + x] = fsi - 6.0 * W[i] * RHO0 * cu;",
+     "d->fn[(size_t)ib * n + x] = fsi + 6.0 * W[i] * RHO0 * cu;",
+     ["test_open_domain_mass_budget", "test_hagen_poiseuille_cylinder"]),
+    ("inlet: profile divided by R instead of R^2",
+     "double v = 1.0 - r2 / (io->R * io->R);",
+     "double v = 1.0 - r2 / io->R;",
+     ["test_open_domain_mass_budget"]),
+    ("outlet: equilibrium of the wrong direction",
+     "d->fn[(size_t)ib * n + x] = feq[ib];",
+     "d->fn[(size_t)ib * n + x] = feq[i];",
+     ["test_open_domain_mass_budget"]),
+    ("iolet mean density: wrong count",
+     "io->mean_rho = cnt[k] ? sr[k] / (double)cnt[k] : RHO0;",
+     "io->mean_rho = cnt[k] ? sr[k] / (double)(cnt[k] + 1) : RHO0;",
+     ["test_hagen_poiseuille_cylinder"]),
+    ("wall shear stress: viscous prefactor",
+     "double pref = -(1.0 - 1.0 / (2.0 * d->tau));",
+     "double pref = -(1.0 - 1.0 / d->tau);",
+     ["test_wall_shear_stress_plane_poiseuille"]),
+    ("Eq. (2): distance ratio inverted",
+     "double ratio = (dp[i] * L[0] * A[i]) / (dp[0] * L[i] * A[0]);",
+     "double ratio = (dp[i] * L[i] * A[i]) / (dp[0] * L[0] * A[0]);",
+     ["test_velocity_factors_conserve_mass", "test_velocity_factors_paper_example"]),
+    ("coupling reverse rule: Eq. (1) solved with the wrong sign",
+     "sum = sum + pv / (1.0 - o->delta);",
+     "sum = sum + pv / (1.0 + o->delta);",
+     ["test_coupled_1to3_reaches_eq2_ratios"]),
+]
+
+
+def _build(src_text, folder, tag):
+    from oracle import build as ob
+    src = os.path.join(folder, f"{tag}.c")
+    with open(src, "w") as fh:
+        fh.write(src_text)
+    return ob.build(src=src, out=os.path.join(folder, f"{tag}.so"))
+
+
+def _run_pins(lib, names):
+    """Run the named pins against the oracle build `lib`; return the set of
+    those that failed."""
+    env = dict(os.environ, ORACLE_LIB_OVERRIDE=lib, OMP_NUM_THREADS="1")
+    sel = " or ".join(names)
+    p = subprocess.run([sys.executable, "-m", "pytest", PINS, "-q", "-rfE", "-p", "no:cacheprovider",
+                        "-m", "not gpu", "-k", sel], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    failed = set(re.findall(r"^(?:FAILED|ERROR) \S+::(\w+)", p.stdout, flags=re.M))
+    ran = re.search(r"(\d+) (passed|failed)", p.stdout)
+    assert ran, p.stdout[-2000:] + p.stderr[-2000:]
+    return failed, p
+
+
+def test_every_mutant_is_caught():
+    with open(SRC) as fh:
+        text = fh.read()
+    for name, old, new, _ in MUTANTS:
+        assert text.count(old) == 1, f"mutation site not found once: {name}"
+    names = sorted({t for *_, pins in MUTANTS for t in pins})
+    with tempfile.TemporaryDirectory() as tmp:
+        jobs = [("control", text, names)]
+        for k, (name, old, new, pins) in enumerate(MUTANTS):
+            jobs.append((name, text.replace(old, new), pins))
+
+        def one(job):
+            tag = f"m{jobs.index(job)}"
+            lib = _build(job[1], tmp, tag)
+            failed, p = _run_pins(lib, job[2])
+            return job[0], job[2], failed, p
+
+        with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
+            results = list(ex.map(one, jobs))
+    problems = []
+    for name, pins, failed, p in results:
+        if name == "control":
+            if failed:
+                problems.append(f"unmodified oracle fails {sorted(failed)}")
+            continue
+        missed = [t for t in pins if t not in failed]
+        if missed:
+            problems.append(f"{name}: {missed} still pass")
+    assert not problems, "\n".join(problems)

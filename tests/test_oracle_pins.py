@@ -16,6 +16,7 @@ import pytest
 import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+_W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)    # rest state f_i = w_i rho0
 
 
 # --------------------------------------------------------------------------
@@ -299,10 +300,13 @@ def test_wall_shear_stress_plane_poiseuille(oracle_mod):
     assert np.abs(wss[edge] - F * (H - 1) / 2).max() / (F * (H - 1) / 2) < 1e-6
 
 
-def test_bouzidi_second_order_vs_bounce_back_first_order(oracle_mod):
-    """Walls a quarter spacing from the outer nodes: linear Bouzidi converges
-    at second order, halfway bounce-back (wall misplaced) at first order."""
-    tau, q = 0.8, 0.25
+@pytest.mark.parametrize("q", [0.1, 0.25])
+def test_bouzidi_second_order_vs_bounce_back_first_order(oracle_mod, q):
+    """Walls a tenth or a quarter of a spacing from the outer nodes (the
+    q < 1/2 branch, interpolating with the second node x - c_i; at q = 0.1 its
+    weights 2q and 1 - 2q differ fourfold): linear Bouzidi converges at second
+    order, halfway bounce-back (wall misplaced) at first order."""
+    tau = 0.8
     errs = {"bz": [], "sbb": []}
     for H in (6, 12, 24):
         width = (H - 1) + 2 * q
@@ -319,6 +323,111 @@ def test_bouzidi_second_order_vs_bounce_back_first_order(oracle_mod):
     assert np.all(order_bz > 1.7), (bz, order_bz)
     assert np.all(order_sb < 1.3), (sb, order_sb)
     assert bz[-1] < sb[-1] / 5
+
+
+def test_bouzidi_far_wall_second_order(oracle_mod):
+    """Walls three quarters of a spacing beyond the outer nodes (q = 3/4, the
+    q >= 1/2 branch of the linear interpolation, which uses the site's own
+    population of the opposite direction): Bouzidi still converges at second
+    order, halfway bounce-back (wall misplaced) at first order."""
+    tau, q = 0.8, 0.75
+    errs = {"bz": [], "sbb": []}
+    for H in (6, 12, 24):
+        width = (H - 1) + 2 * q
+        F = 1e-6 * (6.0 / width) ** 2
+        steps = int(25 * width ** 2 / ((tau - 0.5) / 3) / 10)
+        for key, mode in (("bz", oracle_mod.BOUZIDI), ("sbb", oracle_mod.SBB)):
+            y, ux, _, _ = _channel_profile(oracle_mod, H, tau, F, steps, q=q, mode=mode)
+            nu = (tau - 0.5) / 3
+            exact = F / (2 * nu) * (y + q) * (H - 1 + q - y)
+            errs[key].append(np.sqrt(np.mean((ux - exact) ** 2) / np.mean(exact ** 2)))
+    bz, sb = np.array(errs["bz"]), np.array(errs["sbb"])
+    order_bz = np.log2(bz[:-1] / bz[1:])
+    order_sb = np.log2(sb[:-1] / sb[1:])
+    assert np.all(order_bz > 1.7), (bz, order_bz)
+    assert np.all(order_sb < 1.3), (sb, order_sb)
+    assert bz[-1] < sb[-1] / 5
+
+
+def test_bouzidi_at_half_is_bounce_back(oracle_mod):
+    """With every wall fraction at q = 1/2 the interpolation weights are 1 and
+    0, so Bouzidi walls reproduce halfway bounce-back bit for bit: a cylinder
+    with flow through its inlet and outlet, 200 steps, both wall modes."""
+    geo = synth.cylinder(nz=24)
+    s_, d_ = geo.wall_links()
+    geo.q_site, geo.q_dir = s_, d_
+    geo.q = np.full(s_.size, 0.5, np.float32)
+    runs = []
+    for mode in (oracle_mod.BOUZIDI, oracle_mod.SBB):
+        s = _system(oracle_mod, geo, tau=0.7, mode=mode, u_in=0.02, rho_out=1.001)
+        s.step(200)
+        runs.append(s.f())
+    assert np.abs(runs[1] - _W[:, None]).max() > 1e-4      # the flow is not at rest
+    assert np.array_equal(runs[0], runs[1])
+
+
+def test_bouzidi_without_second_node_is_bounce_back(oracle_mod):
+    """A channel one site high: every wall link's second node x - c_i lies in
+    the opposite wall, so the near-wall branch (q < 1/2) has no fluid node to
+    interpolate with and must fall back to halfway bounce-back, bit for bit;
+    the far-wall branch (q >= 1/2) needs no second node and differs."""
+    geo = synth.channel(nx=3, ny=1, nz=2)
+    s_, d_ = geo.wall_links()
+    geo.q_site, geo.q_dir = s_, d_
+    res = {}
+    for key, q, mode in (("near", 0.25, oracle_mod.BOUZIDI), ("far", 0.75, oracle_mod.BOUZIDI),
+                         ("sbb", 0.5, oracle_mod.SBB)):
+        geo.q = np.full(s_.size, q, np.float32)
+        s = _system(oracle_mod, geo, tau=0.9, mode=mode, F=(2e-6, 0.0, 1e-6))
+        s.step(150)
+        res[key] = s.f()
+    assert np.abs(res["sbb"] - _W[:, None]).max() > 1e-7
+    assert np.array_equal(res["near"], res["sbb"])
+    assert not np.array_equal(res["far"], res["sbb"])
+
+
+def _series_record(oracle_mod, inlet, outlet, steps):
+    geo = synth.tubes(1, radius=2.5, length=4)
+    s = oracle_mod.System(1)
+    s.set_geometry(0, geo)
+    s.set_params(0, 0.8)
+    i0, o0 = geo.iolets
+    s.set_iolet(0, 0, oracle_mod.INLET, i0.centre, i0.normal, i0.radius, *inlet)
+    s.set_iolet(0, 1, oracle_mod.OUTLET, o0.centre, o0.normal, o0.radius, *outlet)
+    s.init()
+    rec = []
+    for _ in range(steps):
+        s.step(1)
+        rec.append(s.last_bc(0))          # the values step t -> t+1 used, t = 0, 1, ...
+    return np.array(rec)
+
+
+def test_waveform_series_period_mean_and_harmonics(oracle_mod):
+    """Boundary series U(t) = a0 + sum_m a_m cos(2 pi m t/T) + b_m sin(2 pi m t/T)
+    (inlet peak velocity and outlet density, Sec. 3.3 pulsatile inlets):
+    sampled at every step over whole periods of integer length it repeats
+    after T steps, its period mean is a0, and the discrete Fourier projections
+    (2/T) sum U cos(2 pi m t/T) and (2/T) sum U sin(2 pi m t/T) recover each a_m
+    and b_m (and give 0 for harmonics the series does not hold)."""
+    rng = np.random.default_rng(20100414 + 40)
+    Ti, To = 64, 48
+    ai, bi = rng.uniform(-2e-3, 2e-3, 5), rng.uniform(-2e-3, 2e-3, 5)
+    ao, bo = rng.uniform(-1e-3, 1e-3, 3), rng.uniform(-1e-3, 1e-3, 3)
+    rec = _series_record(oracle_mod, (0.006, ai, bi, float(Ti)), (1.0005, ao, bo, float(To)),
+                         2 * 192)
+    t = np.arange(rec.shape[0], dtype=np.float64)
+    for col, a0, a, b, T in ((0, 0.006, ai, bi, Ti), (1, 1.0005, ao, bo, To)):
+        U = rec[:, col]
+        assert np.abs(U[T:] - U[:-T]).max() < 1e-15, col
+        one = U[:T]
+        assert abs(one.mean() - a0) < 1e-15, col
+        for m in range(1, T // 2):
+            ph = 2 * np.pi * m * t[:T] / T
+            am = 2.0 / T * np.sum(one * np.cos(ph))
+            bm = 2.0 / T * np.sum(one * np.sin(ph))
+            ea = a[m - 1] if m <= len(a) else 0.0
+            eb = b[m - 1] if m <= len(b) else 0.0
+            assert abs(am - ea) < 1e-12 and abs(bm - eb) < 1e-12, (col, m, am, ea, bm, eb)
 
 
 @pytest.fixture(scope="module")
