@@ -66,7 +66,7 @@ def kernel_source_hash(read=None):
     """Hash of the library code: the kernels, the layout structs they read and
     the host code that orders the sites and builds the schedule."""
     h = hashlib.sha256()
-    for name in ("hl_kernels.hip", "hl_internal.h", "hl_api.cpp"):
+    for name in ("hl_kernels.hip", "hl_internal.h", "hl_api.cpp", "hl_host.h", "hl_layout.cpp"):
         if read is None:
             with open(os.path.join(ROOT, "paper_2010_04144_amd", "csrc", name)) as fh:
                 text = fh.read()

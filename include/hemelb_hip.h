@@ -108,6 +108,13 @@ extern "C" {
 /* with HL_ORDER_BRICK: bricks of 32^3 voxels instead of 16^3 (fewer brick faces,
  * larger groups; HL_E_INVAL without HL_ORDER_BRICK) */
 #define HL_ORDER_BRICK_32 32u
+/* debug: before the first upload, check the planned layout exhaustively on
+ * the host against the caller's site lists (every pull index in range and on
+ * a real site, equal to the caller's neighbour through the site order, int16
+ * deltas decoding to the same site, every site in exactly one work-group);
+ * hl_commit then fails with HL_E_RANGE or HL_E_INVAL and a message instead of
+ * uploading a faulty table.  Costs host time of the order of the planning. */
+#define HL_DEBUG_CHECKS 64u
 
 /* schedule flags */
 #define HL_SCHED_XCD_REMAP 1u /* hand each XCD a contiguous range of site blocks */
@@ -118,6 +125,11 @@ extern "C" {
 #define HL_SCHED_PAIRS 4u     /* bulk kernel with two adjacent sites per lane (vector loads/stores);
                                  ignored with HL_SCHED_FUSED, HL_SCHEME_AA, HL_F16_SCALED and
                                  HL_F16_STOCHASTIC */
+#define HL_SCHED_XCD_BRICKS 16u /* with HL_SCHED_FUSED alone, in a brick layout: the work-groups are cut
+                                 into runs of at least 64 that end only at brick boundaries, and each
+                                 run goes to the XCD holding the fewest so far, so a brick's lines are
+                                 fetched and written through one XCD's L2 while the XCDs sweep the
+                                 site list side by side */
 
 typedef struct hl_ctx hl_ctx;
 
@@ -144,33 +156,48 @@ typedef struct {
 
 /* Create a context on HIP device `device` storing populations in `precision`
  * (HL_F64, HL_F32_OFFSET, HL_F16_OFFSET, HL_F16_SCALED, HL_F16_STOCHASTIC); `flags` is 0 or a combination of
- * HL_ORDER_* bits.  Errors: HL_E_INVAL (bad precision or flags), HL_E_DEVICE
- * (no such device, or not gfx950).  *out is NULL on error. */
+ * HL_ORDER_*, HL_SCHEME_AA and HL_DEBUG_CHECKS bits.  Errors: HL_E_INVAL (bad
+ * precision or flags), HL_E_DEVICE (no such device, or not gfx950).  *out is
+ * NULL on error.  Infrastructure: no passage of the paper defines it. */
 int hl_create(hl_ctx **out, int device, int precision, uint64_t flags);
 
-/* Release the context and its device memory.  NULL is allowed; calling it
- * twice on the same pointer is not. */
+/* Release the context and its device memory after the work queued on its
+ * stream has finished.  NULL is allowed; calling it twice on the same pointer
+ * is not.  Infrastructure: no passage of the paper defines it. */
 void hl_destroy(hl_ctx *ctx);
 
-/* Message for the last failing call on ctx (valid until the next call). */
+/* Message for the last failing call on ctx (valid until the next call).
+ * Infrastructure (no defining passage), as is hl_status_string. */
 const char *hl_last_error(const hl_ctx *ctx);
 
 /* Static text for a status code. */
 const char *hl_status_string(int code);
 
 /* Queue all device work of ctx on `hip_stream` (a hipStream_t; NULL selects
- * the null stream).  The stream must outlive the context's use of it. */
+ * the null stream).  The stream must outlive the context's use of it.  Work
+ * already queued on the previous stream is waited for before the switch, so
+ * nothing on the new stream overlaps it.  HL_E_DEVICE when that wait fails.
+ * Infrastructure: no passage of the paper defines it. */
 int hl_set_stream(hl_ctx *ctx, void *hip_stream);
 
-/* Add an empty domain (one vascular tree or ensemble member) and return its
- * id (0, 1, ... in call order).  Not allowed after the first step. */
+/* Add an empty domain and return its id (0, 1, ... in call order).  A domain
+ * is one instance of the method with its own geometry, relaxation time and
+ * iolets: an arterial or a venous tree of the self-coupled pair (Sec. 2.3:
+ * several instances in one simulation exchanging only boundary averages), or
+ * an ensemble member.  Every domain of a context advances in the same
+ * launches.  HL_E_INVAL for NULL arguments; HL_E_STATE after the first step. */
 int hl_add_domain(hl_ctx *ctx, int32_t *dom_id);
 
 /* ---- geometry ------------------------------------------------------------ */
 
-/* Check a site list without a device.  nbr is int32 [19][n] (direction-major):
+/* Check a site list without a device (Sec. 1: the code works on sparse lists
+ * of fluid sites of vascular geometries; Sec. 2.2: blocks of sites with their
+ * neighbour links).  nbr is int32 [19][n] (direction-major), caller-owned and
+ * only read:
  * nbr[i*n + x] is the caller index of the fluid site at x + c_i, -1 when that
- * voxel is wall, -2-k when it lies beyond the cut plane of iolet k.
+ * voxel is wall, -2-k when it lies beyond the cut plane of iolet k.  Element
+ * offsets are 64-bit, so 19 n may exceed 2^31 (Sec. 2.1: element counts beyond
+ * 32-bit ranges).
  * Errors: HL_E_RANGE (n < 0 or n > 2^31-1, an index >= n, a code below
  * -1-n_iolet, nbr[0][x] != x); HL_E_INVAL (a fluid link without its reverse
  * link, nbr[i][x] = y but nbr[opp(i)][y] != x; a site bordering two iolets). */
@@ -189,10 +216,12 @@ int hl_load_sites(hl_ctx *ctx, int32_t dom, int64_t n, const int32_t *coords, co
                   int32_t n_iolet, int64_t n_q, const int64_t *q_site, const int8_t *q_dir,
                   const float *q);
 
-/* Optional outward or inward unit normals (double [3][n_w]) for wall sites,
- * used by the wall shear stress; sites without one use the normalised
- * negative sum of their wall-link directions.  HL_E_RANGE for a site index
- * outside the domain; HL_E_STATE after the first step. */
+/* Optional unit normals (double [3][n_w], either orientation; copied) of wall
+ * sites site[0..n_w) (caller indices), used by the wall shear stress (Sec. 1
+ * names wall shear stress as the quantity 3D models add); sites without one
+ * use the normalised negative sum of their wall-link directions.  HL_E_INVAL
+ * for NULL arrays with n_w > 0; HL_E_RANGE for a site index outside the
+ * domain; HL_E_STATE after the first step. */
 int hl_set_wall_normals(hl_ctx *ctx, int32_t dom, int64_t n_w, const int64_t *site, const double *nrm);
 
 /* ---- physics --------------------------------------------------------------- */
@@ -267,7 +296,8 @@ int hl_commit(hl_ctx *ctx);
  * hl_set_populations). */
 int hl_step(hl_ctx *ctx, int64_t nsteps);
 
-/* Wait for the context stream; HL_E_DIVERGED as above. */
+/* Wait for the context stream; HL_E_DIVERGED as above.  Infrastructure (no
+ * defining passage), as are hl_get_time and hl_set_drive. */
 int hl_sync(hl_ctx *ctx);
 
 /* Current step counter t. */
@@ -311,7 +341,8 @@ int hl_read_wss_device(hl_ctx *ctx, int32_t dom, void *dptr);
 
 /* Copy the complete dynamic state (both population lattices, outlet velocity
  * history, step counter, coupling values, divergence flag) into buf.  With
- * buf == NULL only *bytes is set.  HL_E_INVAL when *bytes is too small. */
+ * buf == NULL only *bytes is set.  HL_E_INVAL when *bytes is too small.
+ * Infrastructure (checkpoints; no defining passage), as is hl_set_state. */
 int hl_get_state(hl_ctx *ctx, void *buf, size_t *bytes);
 /* Restore a state taken from a context with the same geometry and
  * precision.  HL_E_INVAL on a size, layout or version mismatch. */
@@ -321,9 +352,20 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes);
 
 /* Time candidate schedules for about budget_ms and keep the fastest: work-group
  * size {64, 128, 256} x {split, fused} x {plain, contiguous XCD ranges, XCD
- * runs}, plus the two-sites-per-lane bulk kernel where it applies.  The dynamic
- * state is saved and restored around the trials, so results do not change. */
+ * runs}, the brick-aligned XCD runs in brick layouts, and the two-sites-per-
+ * lane bulk kernel where it applies.  Every candidate is timed once; the three
+ * fastest are then timed five more times each and the one with the lowest
+ * median is kept.  The schedule, drive and dynamic state are restored on every
+ * exit, including errors, so results do not change.  Infrastructure (the
+ * paper's CPU load balancing of Sec. 2.2.1 is prior art, not this): no
+ * defining passage; likewise hl_get_schedule, hl_set_schedule, hl_get_info,
+ * hl_time_kernels and hl_copy_bandwidth. */
 int hl_autotune(hl_ctx *ctx, int budget_ms);
+/* Outcome of the last hl_autotune on ctx: the number of candidates, the
+ * median step time of the kept schedule and of the runner-up (ms), and the
+ * spread (max - min) / median of the kept schedule's repeated timings.
+ * HL_E_STATE before any hl_autotune. */
+int hl_autotune_report(hl_ctx *ctx, int32_t *n_candidates, double *best_ms, double *runner_up_ms, double *spread);
 int hl_get_schedule(hl_ctx *ctx, int32_t *block_size, int32_t *flags);
 /* block_size in {64, 128, 256}; flags of HL_SCHED_*. */
 int hl_set_schedule(hl_ctx *ctx, int32_t block_size, int32_t flags);
@@ -338,6 +380,27 @@ int hl_get_info(hl_ctx *ctx, hl_info *out);
  * one-work-group finalize kernel is not included.  The steps are real steps
  * (t advances). */
 int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd);
+
+/* ---- coupling construction (host only, no context or device) ------------- */
+
+/* The distance-based map of Sec. 3: arterial outlets in index order each take
+ * the nearest venous inlet not yet taken (ties: lowest inlet index), so every
+ * outlet gets one when there are at least as many inlets; every inlet left
+ * then joins its nearest outlet (ties: lowest outlet index).  out_c: double
+ * [3][n_out] and in_c: double [3][n_in] iolet centres (caller-owned, read
+ * only).  Writes owner[j] (outlet of inlet j) and dist[j] (the centre distance,
+ * L_i of Eq. (1)-(2)) for j < n_in.  HL_E_INVAL for NULL arrays, n_out < 1 or
+ * n_in < 0. */
+int hl_coupling_map(int32_t n_out, const double *out_c, int32_t n_in, const double *in_c, int32_t *owner,
+                    double *dist);
+
+/* Eq. (2) of Sec. 3: the velocity factor v_i / v_0 of each of the nv veins of
+ * one arterial outlet, from their pressure-drop factors dp[i] = dP_i / P_0,
+ * distances L[i] and areas A[i] and the outlet area A0 (arrays of nv doubles,
+ * caller-owned).  The factors satisfy sum_i A_i v_i = A_0 v_0 (the veins carry
+ * the outlet's flow).  Writes v[0..nv).  HL_E_INVAL for nv < 1, NULL arrays or
+ * a non-positive or non-finite input. */
+int hl_velocity_factors(int32_t nv, const double *dp, const double *L, const double *A, double A0, double *v);
 
 /* Measured copy ceiling (no context): copy `bytes` bytes from src to dst, two
  * device buffers of the current device that the caller owns (16-byte aligned,

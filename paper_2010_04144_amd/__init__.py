@@ -13,10 +13,12 @@ import ctypes as ct
 import numpy as np
 
 from . import _lib
-from ._lib import (HL_ALTERNATE, HL_BOTH_EACH_STEP, HL_DRIVE_GRAPH, HL_DRIVE_LAUNCH,  # noqa: F401
+from ._lib import (HL_ALTERNATE, HL_BOTH_EACH_STEP, HL_DEBUG_CHECKS, HL_DRIVE_GRAPH, HL_DRIVE_LAUNCH,  # noqa: F401
                    HL_E_DEVICE, HL_E_DIVERGED, HL_E_INVAL, HL_E_NOMEM, HL_E_RANGE, HL_E_STATE,
-                   HL_F16_OFFSET, HL_F16_SCALED, HL_F16_STOCHASTIC, HL_F32_OFFSET, HL_F64, HL_INLET_VEL, HL_OK, HL_OUTLET_P,
-                   HL_ORDER_BOUNDARY_MORTON, HL_ORDER_BRICK, HL_ORDER_BRICK_32, HL_ORDER_BULK_MORTON, HL_ORDER_INTERLEAVE, HL_SCHED_FUSED, HL_SCHED_PAIRS, HL_SCHEME_AA, HL_SCHED_XCD_REMAP, HL_SCHED_XCD_RUNS, HL_W_MACH, HL_W_TAU, HL_WALL_BOUZIDI, HL_WALL_SBB, hl_info)
+                   HL_F16_OFFSET, HL_F16_SCALED, HL_F16_STOCHASTIC, HL_F32_OFFSET, HL_F64, HL_INLET_VEL, HL_OK,
+                   HL_OUTLET_P, HL_ORDER_BOUNDARY_MORTON, HL_ORDER_BRICK, HL_ORDER_BRICK_32, HL_ORDER_BULK_MORTON,
+                   HL_ORDER_INTERLEAVE, HL_SCHED_FUSED, HL_SCHED_PAIRS, HL_SCHED_XCD_BRICKS, HL_SCHED_XCD_REMAP,
+                   HL_SCHED_XCD_RUNS, HL_SCHEME_AA, HL_W_MACH, HL_W_TAU, HL_WALL_BOUZIDI, HL_WALL_SBB, hl_info)
 
 PRECISIONS = {"f64": HL_F64, "f32": HL_F32_OFFSET, "f16": HL_F16_OFFSET, "f16w": HL_F16_SCALED, "f16sr": HL_F16_STOCHASTIC}
 
@@ -59,6 +61,31 @@ def hl_copy_bandwidth(dst, src, nbytes, reps=20, stream=None):
 
 def _pd(a):
     return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def hl_coupling_map(outlet_centres, inlet_centres):
+    """Sec. 3 distance map (host only): (owner int32 [n_in], dist float64
+    [n_in]) for centres given as (n, 3) arrays."""
+    oc = np.ascontiguousarray(np.asarray(outlet_centres, dtype=np.float64).reshape(-1, 3).T)
+    ic = np.ascontiguousarray(np.asarray(inlet_centres, dtype=np.float64).reshape(-1, 3).T)
+    n_out, n_in = oc.shape[1], ic.shape[1]
+    owner = np.zeros(n_in, np.int32)
+    dist = np.zeros(n_in)
+    rc = lib().hl_coupling_map(n_out, _pd(oc), n_in, _pd(ic), owner.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                               _pd(dist))
+    if rc != HL_OK:
+        raise HLError(rc, f"hl_coupling_map failed: {status_string(rc)}")
+    return owner, dist
+
+
+def hl_velocity_factors(dp, L, A, A0):
+    """Eq. (2) (host only): v_i / v_0 for the veins of one arterial outlet."""
+    dp, L, A = (np.ascontiguousarray(v, dtype=np.float64).ravel() for v in (dp, L, A))
+    v = np.zeros(dp.size)
+    rc = lib().hl_velocity_factors(dp.size, _pd(dp), _pd(L), _pd(A), float(A0), _pd(v))
+    if rc != HL_OK:
+        raise HLError(rc, f"hl_velocity_factors failed: {status_string(rc)}")
+    return v
 
 
 class Context:
@@ -262,6 +289,13 @@ class Context:
 
     def autotune(self, budget_ms=500):
         return self._chk(self._l.hl_autotune(self._h, int(budget_ms)), "hl_autotune")
+
+    def autotune_report(self):
+        """(candidates, best ms/step, runner-up ms/step, spread of the best's repeats)."""
+        n, b, r, sp = ct.c_int32(), ct.c_double(), ct.c_double(), ct.c_double()
+        self._chk(self._l.hl_autotune_report(self._h, ct.byref(n), ct.byref(b), ct.byref(r), ct.byref(sp)),
+                  "hl_autotune_report")
+        return n.value, b.value, r.value, sp.value
 
     def schedule(self):
         b, f = ct.c_int32(), ct.c_int32()

@@ -45,6 +45,8 @@ HL_SCHED_PAIRS = 4
 HL_SCHED_XCD_RUNS = 8
 HL_SCHEME_AA = 16
 HL_ORDER_BRICK_32 = 32
+HL_DEBUG_CHECKS = 64
+HL_SCHED_XCD_BRICKS = 16
 
 
 class hl_info(ct.Structure):
@@ -118,6 +120,9 @@ SIGNATURES = {
     "hl_get_info": (_I, [_P, ct.POINTER(hl_info)]),
     "hl_time_kernels": (_I, [_P, _I64, _pD, _pD]),
     "hl_copy_bandwidth": (_I, [_P, _P, _I64, _I32, _P, _pD]),
+    "hl_autotune_report": (_I, [_P, _pI32, _pD, _pD, _pD]),
+    "hl_coupling_map": (_I, [_I32, _pD, _I32, _pD, _pI32, _pD]),
+    "hl_velocity_factors": (_I, [_I32, _pD, _pD, _pD, _D, _pD]),
 }
 
 _lib = None

@@ -23,7 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I", INC, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-fno-gpu-flush-denormals-to-zero", "-Wall", "-Wno-unused-result"]
-SOURCES = ["hl_kernels.hip", "hl_api.cpp", "hl_ceiling.hip"]
+SOURCES = ["hl_kernels.hip", "hl_api.cpp", "hl_layout.cpp", "hl_ceiling.hip"]
 
 
 def build(verbose=False, extra=()):

@@ -1,4 +1,5 @@
-"""Host-side construction of the arterial-venous coupling (Sec. 3).
+"""Host-side construction of the arterial-venous coupling (Sec. 3), marshalled
+to the library's C ABI (``hl_coupling_map``, ``hl_velocity_factors``).
 
 * ``coupling_map``: the greedy distance-based mapping described in Sec. 3.
   Arterial outlets are visited in index order; each takes the closest venous
@@ -8,47 +9,30 @@
   of each pair, which Eq. (1) uses as L_i.
 * ``velocity_factors``: Eq. (2), the velocity scale factor v_i/v_0 of each of
   the N veins of one outlet from the pressure-drop factors dP_i/P_0, the
-  distances L_i and the areas A_i (vein) and A_0 (outlet).  It follows from
-  dP_i = k_i q_i L_i with k_i proportional to 1/A_i and q_0 = sum_i q_i.
+  distances L_i and the areas A_i (vein) and A_0 (outlet).
 * ``build_pairs``: both together, giving the argument lists of ``hl_couple``.
 
-These produce the inputs of the device-side exchange; the exchange itself
-(forward and reverse boundary values each step) runs in the library.
+The arithmetic of both runs in the library (host code, no device needed);
+the exchange itself (forward and reverse boundary values each step) runs in
+its kernels.
 """
 from __future__ import annotations
 
 import numpy as np
 
+from . import hl_coupling_map, hl_velocity_factors
+
 
 def coupling_map(outlet_centres, inlet_centres):
     """Return (outlet_of_inlet int array, distance float array), one entry per
-    venous inlet."""
-    a = np.asarray(outlet_centres, dtype=np.float64).reshape(-1, 3)
-    v = np.asarray(inlet_centres, dtype=np.float64).reshape(-1, 3)
-    na, nv = a.shape[0], v.shape[0]
-    dist = np.sqrt(((a[:, None, :] - v[None, :, :]) ** 2).sum(-1))
-    owner = np.full(nv, -1, dtype=np.int64)
-    free = np.ones(nv, dtype=bool)
-    for i in range(na):
-        if not free.any():
-            break
-        cand = np.where(free, dist[i], np.inf)
-        j = int(np.argmin(cand))          # lowest index among equal distances
-        owner[j] = i
-        free[j] = False
-    for j in np.flatnonzero(free):
-        owner[j] = int(np.argmin(dist[:, j]))
-    return owner, dist[owner, np.arange(nv)]
+    venous inlet; centres are (n, 3) arrays."""
+    owner, dist = hl_coupling_map(outlet_centres, inlet_centres)
+    return owner.astype(np.int64), dist
 
 
 def velocity_factors(dp, L, A, A0):
-    """Eq. (2) for the veins of one arterial outlet (first vein as the
-    reference of the ratios, as printed)."""
-    dp = np.asarray(dp, dtype=np.float64)
-    L = np.asarray(L, dtype=np.float64)
-    A = np.asarray(A, dtype=np.float64)
-    r = (dp * L[0] * A) / (dp[0] * L * A[0])
-    return (A0 / A) * r / r.sum()
+    """Eq. (2) for the veins of one arterial outlet."""
+    return hl_velocity_factors(dp, L, A, A0)
 
 
 def build_pairs(dom_a, outlets, outlet_centres, outlet_areas, dom_b, inlets, inlet_centres, inlet_areas, dp):

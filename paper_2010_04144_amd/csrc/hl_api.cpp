@@ -14,87 +14,13 @@
 #include <vector>
 
 #include "hemelb_hip.h"
-#include "hl_internal.h"
+#include "hl_host.h"
 
 using hl::Q;
-
-namespace {
-
-constexpr int CXh[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int CYh[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int CZh[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-inline int opp_h(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-
-// Spread the low 21 bits of v to every third bit.
-inline uint64_t spread3(uint64_t v) {
-    v &= 0x1fffff;
-    v = (v | v << 32) & 0x1f00000000ffffULL;
-    v = (v | v << 16) & 0x1f0000ff0000ffULL;
-    v = (v | v << 8) & 0x100f00f00f00f00fULL;
-    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
-    v = (v | v << 2) & 0x1249249249249249ULL;
-    return v;
-}
-
-struct Series {
-    double a0 = 0.0;
-    int nh = 0;
-    double a[hl::MAXH] = {0}, b[hl::MAXH] = {0};
-    double period = 1.0;
-    double at(double t) const {
-        double v = a0;
-        for (int m = 1; m <= nh; ++m) {
-            const double ph = 2.0 * M_PI * (double)m * t / period;
-            v = v + a[m - 1] * std::cos(ph) + b[m - 1] * std::sin(ph);
-        }
-        return v;
-    }
-    double bound() const {
-        double v = std::fabs(a0);
-        for (int m = 0; m < nh; ++m) v += std::fabs(a[m]) + std::fabs(b[m]);
-        return v;
-    }
-};
-
-struct IoletH {
-    int kind = hl::KIND_INLET;
-    double c[3] = {0, 0, 0}, nrm[3] = {0, 0, 1}, R = 1.0;
-    Series wave;
-    bool coupled = false;
-};
-
-struct Domain {
-    int64_t n = 0;
-    std::vector<int32_t> coords, nbr;
-    std::vector<int64_t> q_site;
-    std::vector<int8_t> q_dir;
-    std::vector<float> q;
-    std::vector<int64_t> wn_site;
-    std::vector<double> wn;
-    int32_t n_iolet = 0;
-    std::vector<IoletH> io;
-    double tau = 1.0;
-    int wall_mode = hl::WALL_SBB;
-    double F0[3] = {0, 0, 0}, omega = 0.0;
-    // after commit
-    std::vector<int64_t> c2g;
-    int32_t io_base = 0;
-    int64_t *d_c2g = nullptr;
-};
-
-struct PairH {
-    int da, ka, db, kb;
-    double s, delta;
-};
-
-// a contiguous internal range of one class in one domain
-struct Range {
-    int64_t start, count;
-    int32_t seg, tag;
-    bool mixed = false;  // interleaved bulk and wall sites, split per work-group
-};
-
-}  // namespace
+using hl::Domain;
+using hl::IoletH;
+using hl::PairH;
+using hl::Series;
 
 struct hl_ctx {
     int device = 0, precision = 0;
@@ -113,21 +39,18 @@ struct hl_ctx {
     int drive = HL_DRIVE_GRAPH;
     int steps_per_graph = 16;
     int64_t t_host = 0;
-    // layout
-    int64_t N = 0, NB = 0, IO0 = 0, Nb = 0, Nio = 0, Npad = 0;
-    int64_t n_sites = 0, n_bulk_sites = 0, n_io_sites = 0;
-    std::vector<Range> ranges;
-    std::vector<uint8_t> site_wall;  // interleaved layout: 1 where a site has a boundary link
-    std::vector<hl::Entry> entries, entries2;
-    int n_bulk_blocks = 0, n_bnd_blocks = 0;
-    std::vector<hl::SegDev> hseg;
-    std::vector<hl::IoletDev> hio;
-    std::vector<hl::PairDev> hpairs;
+    hl::Layout L;  // planned layout and schedule
+    bool debug_checks = false;
+    // last hl_autotune: candidates, median ms/step of the kept and the
+    // runner-up schedule, spread of the kept one's repeats
+    int32_t tune_n = 0;
+    double tune_best = 0.0, tune_second = 0.0, tune_spread = 0.0;
     // device memory
     void *lat[2] = {nullptr, nullptr};
     int32_t *d_src = nullptr;
     int16_t *d_d16 = nullptr;
-    int64_t n_near_sites = 0;
+    int32_t *d_emap = nullptr;
+    std::vector<int64_t *> d_c2g;  // per domain: caller index -> internal index (device reads)
     float *d_bq = nullptr;
     double *d_bphi = nullptr, *d_bnrm = nullptr;
     void *d_up[2] = {nullptr, nullptr};
@@ -200,10 +123,10 @@ void free_device(hl_ctx *c) {
                   c->d_entries, c->d_entries2, c->d_seg, c->d_io, c->d_pairs, c->d_ctrl, c->d_partials, c->d_stats,
                   c->d_bc, c->d_held, c->d_obs, c->d_fbuf};
     for (void *p : ps) dfree(p);
-    for (auto &d : c->doms) {
-        dfree(d.d_c2g);
-        d.d_c2g = nullptr;
-    }
+    for (auto &p : c->d_c2g) dfree(p);
+    c->d_c2g.clear();
+    dfree(c->d_emap);
+    c->d_emap = nullptr;
     c->lat[0] = c->lat[1] = nullptr;
     c->d_src = nullptr;
     c->d_d16 = nullptr;
@@ -220,25 +143,14 @@ void free_device(hl_ctx *c) {
     c->dev_bytes = 0;
 }
 
-hl::SegDev seg_of(const Domain &d) {
-    hl::SegDev s{};
-    s.inv_tau = 1.0 / d.tau;
-    s.guo_pref = 1.0 - 1.0 / (2.0 * d.tau);
-    for (int k = 0; k < 3; ++k) s.F0[k] = d.F0[k];
-    s.omega = d.omega;
-    s.wall_mode = d.wall_mode;
-    s.has_force = (d.F0[0] != 0.0 || d.F0[1] != 0.0 || d.F0[2] != 0.0) ? 1 : 0;
-    return s;
-}
-
 hl::KArgs make_args(hl_ctx *c) {
     hl::KArgs a{};
-    a.N = c->N;
-    a.NB = c->NB;
-    a.IO0 = c->IO0;
-    a.Nb = c->Nb;
-    a.Nio = c->Nio;
-    a.Npad = c->Npad;
+    a.N = c->L.N;
+    a.NB = c->L.NB;
+    a.IO0 = c->L.IO0;
+    a.Nb = c->L.Nb;
+    a.Nio = c->L.Nio;
+    a.Npad = c->L.Npad;
     a.lat0 = c->lat[0];
     a.lat1 = c->lat[1];
     a.src = c->d_src;
@@ -252,14 +164,14 @@ hl::KArgs make_args(hl_ctx *c) {
     a.entries2 = c->d_entries2;
     a.n_pairs_blocks = ((c->sched_flags & HL_SCHED_PAIRS) && !(c->sched_flags & HL_SCHED_FUSED) && !c->aa &&
                         c->precision != hl::PREC_F16W && c->precision != hl::PREC_F16SR)
-                           ? (int32_t)c->entries2.size() : 0;
+                           ? (int32_t)c->L.entries2.size() : 0;
     a.seg = c->d_seg;
     a.io = c->d_io;
     a.pairs = c->d_pairs;
-    a.n_io = (int32_t)c->hio.size();
-    a.n_pairs = (int32_t)c->hpairs.size();
+    a.n_io = (int32_t)c->L.hio.size();
+    a.n_pairs = (int32_t)c->L.hpairs.size();
     a.io_e0 = a.io_e1 = 0;
-    for (const auto &io : c->hio) {
+    for (const auto &io : c->L.hio) {
         if (io.e_hi <= io.e_lo) continue;
         if (a.io_e0 == a.io_e1) {
             a.io_e0 = io.e_lo;
@@ -271,6 +183,8 @@ hl::KArgs make_args(hl_ctx *c) {
     }
     a.couple_mode = c->couple_mode;
     a.xcd_remap = !(c->sched_flags & HL_SCHED_XCD_REMAP) ? 0 : ((c->sched_flags & HL_SCHED_XCD_RUNS) ? 64 : 1);
+    a.emap = c->L.emap.empty() ? nullptr : c->d_emap;
+    a.n_emap = (int32_t)c->L.emap.size();
     a.ctrl = c->d_ctrl;
     a.aa = c->aa ? 1 : 0;
     a.partials = c->d_partials;
@@ -283,59 +197,6 @@ hl::KArgs make_args(hl_ctx *c) {
     return a;
 }
 
-// Split the class ranges into work-group entries of at most `block` sites:
-// entries for the bulk kernel first, then those for the boundary kernel.  In
-// the interleaved layout a chunk of a mixed range goes to the bulk kernel
-// when none of its sites has a boundary link.  The fused schedule keeps every
-// entry in storage order for a single launch (n_bulk_blocks = 0).
-
-void build_entries(hl_ctx *c) {
-    std::vector<hl::Entry> bulk, bnd;
-    for (auto &io : c->hio) io.e_lo = io.e_hi = 0;
-    for (const Range &g : c->ranges) {
-        for (int64_t off = 0; off < g.count; off += c->block) {
-            hl::Entry e;
-            e.start = (int32_t)(g.start + off);
-            e.count = (int32_t)std::min<int64_t>(c->block, g.count - off);
-            e.seg = g.seg;
-            e.tag = g.tag;
-            if (g.mixed) {
-                bool wall = false;
-                for (int32_t k = 0; k < e.count && !wall; ++k) wall = c->site_wall[(size_t)e.start + k] != 0;
-                e.tag = wall ? hl::K_WALL : hl::K_BULK;
-            }
-            const int ek = hl::tag_class(e.tag);
-            if ((ek == hl::K_BULK || ek == hl::K_NEAR) && !(c->sched_flags & HL_SCHED_FUSED))
-                bulk.push_back(e);
-            else
-                bnd.push_back(e);
-        }
-    }
-    c->entries = bulk;
-    c->entries.insert(c->entries.end(), bnd.begin(), bnd.end());
-    c->entries2.clear();
-    for (const hl::Entry &e : bulk) {
-        // merge consecutive bulk entries of one range into chunks of 2 x block
-        if (!c->entries2.empty()) {
-            hl::Entry &l = c->entries2.back();
-            if (l.seg == e.seg && l.start + l.count == e.start && l.count + e.count <= 2 * c->block) {
-                l.count += e.count;
-                continue;
-            }
-        }
-        c->entries2.push_back(e);
-    }
-    c->n_bulk_blocks = (int)bulk.size();
-    c->n_bnd_blocks = (int)bnd.size();
-    for (int e = 0; e < (int)c->entries.size(); ++e) {
-        const hl::Entry &en = c->entries[e];
-        if (hl::tag_class(en.tag) != hl::K_IOLET) continue;
-        auto &io = c->hio[hl::tag_iolet(en.tag)];
-        if (io.e_hi == 0) io.e_lo = e;
-        io.e_hi = e + 1;
-    }
-}
-
 int upload_schedule(hl_ctx *c) {
     dfree(c->d_entries);
     dfree(c->d_entries2);
@@ -344,16 +205,22 @@ int upload_schedule(hl_ctx *c) {
     c->d_entries2 = nullptr;
     c->d_partials = nullptr;
     int rc;
-    if ((rc = dalloc(c, &c->d_entries, c->entries.size())) != HL_OK) return rc;
-    if ((rc = dalloc(c, &c->d_entries2, c->entries2.size())) != HL_OK) return rc;
-    if (!c->entries2.empty())
-        HIPC(c, hipMemcpy(c->d_entries2, c->entries2.data(), c->entries2.size() * sizeof(hl::Entry),
+    if ((rc = dalloc(c, &c->d_entries, c->L.entries.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_entries2, c->L.entries2.size())) != HL_OK) return rc;
+    if (!c->L.entries2.empty())
+        HIPC(c, hipMemcpy(c->d_entries2, c->L.entries2.data(), c->L.entries2.size() * sizeof(hl::Entry),
                           hipMemcpyHostToDevice));
-    if ((rc = dalloc(c, &c->d_partials, 2 * c->entries.size())) != HL_OK) return rc;
-    HIPC(c, hipMemcpy(c->d_entries, c->entries.data(), c->entries.size() * sizeof(hl::Entry),
+    if ((rc = dalloc(c, &c->d_partials, 2 * c->L.entries.size())) != HL_OK) return rc;
+    dfree(c->d_emap);
+    c->d_emap = nullptr;
+    if (!c->L.emap.empty()) {
+        if ((rc = dalloc(c, &c->d_emap, c->L.emap.size())) != HL_OK) return rc;
+        HIPC(c, hipMemcpy(c->d_emap, c->L.emap.data(), c->L.emap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    HIPC(c, hipMemcpy(c->d_entries, c->L.entries.data(), c->L.entries.size() * sizeof(hl::Entry),
                       hipMemcpyHostToDevice));
-    if (!c->hio.empty())
-        HIPC(c, hipMemcpy(c->d_io, c->hio.data(), c->hio.size() * sizeof(hl::IoletDev), hipMemcpyHostToDevice));
+    if (!c->L.hio.empty())
+        HIPC(c, hipMemcpy(c->d_io, c->L.hio.data(), c->L.hio.size() * sizeof(hl::IoletDev), hipMemcpyHostToDevice));
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
     c->graph_steps = 0;
@@ -366,9 +233,9 @@ int launch_steps_plain(hl_ctx *c, int64_t n, hipStream_t st, int64_t t0) {
     const hl::KArgs a = make_args(c);
     const bool fused = (c->sched_flags & HL_SCHED_FUSED) != 0;
     for (int64_t k = 0; k < n; ++k) {
-        int e = c->aa ? hl::launch_aa_step(c->precision, a, c->n_bulk_blocks, c->n_bnd_blocks, c->block, st, 0, fused,
+        int e = c->aa ? hl::launch_aa_step(c->precision, a, c->L.n_bulk_blocks, c->L.n_bnd_blocks, c->block, st, 0, fused,
                                            (int)((t0 + k) & 1))
-                      : hl::launch_step(c->precision, a, c->n_bulk_blocks, c->n_bnd_blocks, c->block, st, 0, fused);
+                      : hl::launch_step(c->precision, a, c->L.n_bulk_blocks, c->L.n_bnd_blocks, c->block, st, 0, fused);
         if (e != 0) return fail(c, HL_E_DEVICE, "step launch failed: %s", hipGetErrorString((hipError_t)e));
     }
     return HL_OK;
@@ -424,9 +291,9 @@ int run_steps(hl_ctx *c, int64_t n) {
 
 int upload_params(hl_ctx *c) {
     if (!c->committed) return HL_OK;
-    for (size_t d = 0; d < c->doms.size(); ++d) c->hseg[d] = seg_of(c->doms[d]);
+    for (size_t d = 0; d < c->doms.size(); ++d) c->L.hseg[d] = hl::seg_of(c->doms[d]);
     HIPC(c, hipStreamSynchronize(c->stream));
-    HIPC(c, hipMemcpy(c->d_seg, c->hseg.data(), c->hseg.size() * sizeof(hl::SegDev), hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_seg, c->L.hseg.data(), c->L.hseg.size() * sizeof(hl::SegDev), hipMemcpyHostToDevice));
     return HL_OK;
 }
 
@@ -436,7 +303,7 @@ int refresh_series(hl_ctx *c, int32_t dom, int32_t k) {
     if (!c->committed) return HL_OK;
     Domain &d = c->doms[dom];
     const int g = d.io_base + k;
-    hl::IoletDev &io = c->hio[g];
+    hl::IoletDev &io = c->L.hio[g];
     const Series &s = d.io[k].wave;
     io.a0 = s.a0;
     io.nh = s.nh;
@@ -449,7 +316,7 @@ int refresh_series(hl_ctx *c, int32_t dom, int32_t k) {
     HIPC(c, hipMemcpy(c->d_io + g, &io, sizeof io, hipMemcpyHostToDevice));
     if (!io.coupled) {
         const double v = s.at((double)c->t_host);
-        HIPC(c, hipMemcpy(c->d_bc + (c->t_host & 1) * c->hio.size() + g, &v, sizeof v, hipMemcpyHostToDevice));
+        HIPC(c, hipMemcpy(c->d_bc + (c->t_host & 1) * c->L.hio.size() + g, &v, sizeof v, hipMemcpyHostToDevice));
     }
     return HL_OK;
 }
@@ -465,12 +332,12 @@ int read_nan(hl_ctx *c) {
 
 int observe(hl_ctx *c, bool with_f) {
     int rc;
-    if (!c->d_obs && (rc = dalloc(c, &c->d_obs, 5 * (size_t)c->N)) != HL_OK) return rc;
-    if (with_f && !c->d_fbuf && (rc = dalloc(c, &c->d_fbuf, (size_t)Q * c->N)) != HL_OK) return rc;
+    if (!c->d_obs && (rc = dalloc(c, &c->d_obs, 5 * (size_t)c->L.N)) != HL_OK) return rc;
+    if (with_f && !c->d_fbuf && (rc = dalloc(c, &c->d_fbuf, (size_t)Q * c->L.N)) != HL_OK) return rc;
     if (!with_f && c->obs_t == c->t_host) return HL_OK;
     hl::KArgs a = make_args(c);
     a.fout = with_f ? c->d_fbuf : nullptr;
-    int e = hl::launch_observe(c->precision, a, (int)c->entries.size(), c->block, c->stream);
+    int e = hl::launch_observe(c->precision, a, (int)c->L.entries.size(), c->block, c->stream);
     if (e != 0) return fail(c, HL_E_DEVICE, "observe launch failed: %s", hipGetErrorString((hipError_t)e));
     c->obs_t = c->t_host;
     return HL_OK;
@@ -486,9 +353,9 @@ int reinit(hl_ctx *c) {
         HIPC(c, hipStreamSynchronize(c->stream));
         const int one = 1;
         HIPC(c, hipMemcpy(&c->d_ctrl->direct, &one, sizeof one, hipMemcpyHostToDevice));
-        e = hl::launch_aa_moments(c->precision, a, (int)c->entries.size(), c->block, c->stream, (int)(c->t_host & 1));
+        e = hl::launch_aa_moments(c->precision, a, (int)c->L.entries.size(), c->block, c->stream, (int)(c->t_host & 1));
     } else {
-        e = hl::launch_init(c->precision, a, (int)c->entries.size(), c->block, c->stream);
+        e = hl::launch_init(c->precision, a, (int)c->L.entries.size(), c->block, c->stream);
     }
     if (e != 0) return fail(c, HL_E_DEVICE, "init launch failed: %s", hipGetErrorString((hipError_t)e));
     c->obs_t = -1;
@@ -502,7 +369,7 @@ int reinit(hl_ctx *c) {
 int ensure_stats(hl_ctx *c) {
     if (c->stats_t == c->t_host) return HL_OK;
     hl::KArgs a = make_args(c);
-    int e = hl::launch_aa_moments(c->precision, a, (int)c->entries.size(), c->block, c->stream, (int)(c->t_host & 1));
+    int e = hl::launch_aa_moments(c->precision, a, (int)c->L.entries.size(), c->block, c->stream, (int)(c->t_host & 1));
     if (e != 0) return fail(c, HL_E_DEVICE, "moments launch failed: %s", hipGetErrorString((hipError_t)e));
     c->stats_t = c->t_host;
     return HL_OK;
@@ -510,365 +377,46 @@ int ensure_stats(hl_ctx *c) {
 
 int commit(hl_ctx *c) {
     if (c->committed) return HL_OK;
-    int64_t total = 0;
-    for (auto &d : c->doms) total += d.n;
-    if (total == 0) return fail(c, HL_E_STATE, "no domain holds a site");
-    if (total > INT32_MAX) return fail(c, HL_E_RANGE, "more than 2^31-1 sites in one context");
     HIPC(c, hipSetDevice(c->device));
+    int rc = hl::plan_layout(c->doms, c->pairs, c->order_flags, c->L, c->err);
+    if (rc != HL_OK) return rc;
+    hl::plan_schedule(c->L, c->block, c->sched_flags);
+    if (c->debug_checks && (rc = hl::check_layout(c->doms, c->L, c->block, c->err)) != HL_OK) return rc;
     const int D = (int)c->doms.size();
-
-    // classes: 0 bulk, 1 wall only, 2 iolet k
-    std::vector<std::vector<int32_t>> cls(D);  // -1 bulk, -2 wall, k >= 0 iolet
-    int32_t io_count = 0;
-    for (int d = 0; d < D; ++d) {
-        Domain &dm = c->doms[d];
-        dm.io_base = io_count;
-        io_count += dm.n_iolet;
-        cls[d].assign(dm.n, -1);
-        for (int64_t x = 0; x < dm.n; ++x) {
-            int32_t k = -1;
-            bool wall = false;
-            for (int i = 1; i < Q; ++i) {
-                const int32_t v = dm.nbr[(size_t)i * dm.n + x];
-                if (v == -1) wall = true;
-                if (v <= -2) k = -2 - v;
-            }
-            cls[d][x] = k >= 0 ? k : (wall ? -2 : -1);
-        }
-    }
-    c->n_sites = total;
-    c->n_bulk_sites = 0;
-    c->n_io_sites = 0;
-    for (int d = 0; d < D; ++d)
-        for (auto v : cls[d]) {
-            if (v == -1) ++c->n_bulk_sites;
-            if (v >= 0) ++c->n_io_sites;
-        }
-    // internal order: bulk, wall, iolet groups; inside a group caller order or
-    // Morton order of the coordinates
-    c->ranges.clear();
-    int64_t pos = 0;
-    // every group starts on a whole tile: a work-group's wavefronts then own
-    // whole tiles, and no tile row is written by two work-groups
-    auto align_tile = [&]() { pos = (pos + hl::TILE - 1) & ~(int64_t)(hl::TILE - 1); };
-    auto place = [&](int d, int32_t key, bool morton) {
-        Domain &dm = c->doms[d];
-        align_tile();
-        std::vector<int64_t> idx;
-        for (int64_t x = 0; x < dm.n; ++x)
-            if (cls[d][x] == key) idx.push_back(x);
-        if (morton) {
-            std::vector<std::pair<uint64_t, int64_t>> kv(idx.size());
-            for (size_t m = 0; m < idx.size(); ++m) {
-                const int64_t x = idx[m];
-                const uint64_t mx = (uint64_t)(dm.coords[x] + (1 << 20));
-                const uint64_t my = (uint64_t)(dm.coords[(size_t)dm.n + x] + (1 << 20));
-                const uint64_t mz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] + (1 << 20));
-                kv[m] = {spread3(mx) | (spread3(my) << 1) | (spread3(mz) << 2), x};
-            }
-            std::sort(kv.begin(), kv.end());
-            for (size_t m = 0; m < idx.size(); ++m) idx[m] = kv[m].second;
-        }
-        for (int64_t x : idx) dm.c2g[x] = pos++;
-        return (int64_t)idx.size();
-    };
-    const bool mb = (c->order_flags & HL_ORDER_BULK_MORTON) != 0;
-    const bool mw = (c->order_flags & HL_ORDER_BOUNDARY_MORTON) != 0;
-    const bool inter = (c->order_flags & HL_ORDER_INTERLEAVE) != 0;
-    const bool brick = (c->order_flags & HL_ORDER_BRICK) != 0;
-    if (brick) {
-        // per domain: bricks (16^3, or 32^3 with HL_ORDER_BRICK_32) in
-        // lexicographic brick order; inside a brick the near bulk sites, the
-        // other bulk sites, then the wall sites, each in lexicographic order
-        const int bb = (c->order_flags & HL_ORDER_BRICK_32) ? 5 : 4;  // log2 of the brick edge
-        const uint64_t bm = (1u << bb) - 1;
-        // Bulk sites whose 18 upstream sites all lie in their own brick (and
-        // are not iolet sites) form a group of their own (class 0, tagged
-        // K_NEAR when their pull deltas fit in int16, checked once the order
-        // is final); other bulk sites class 1; wall sites whose fluid upstream
-        // sites satisfy the same condition class 2 (K_NEARWALL), other wall
-        // sites class 3.
-        c->site_wall.clear();
-        for (int d = 0; d < D; ++d) {
-            Domain &dm = c->doms[d];
-            dm.c2g.assign(dm.n, -1);
-            std::vector<std::pair<uint64_t, int64_t>> kv;
-            int64_t mn[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
-            for (int64_t x = 0; x < dm.n; ++x)
-                for (int a = 0; a < 3; ++a) mn[a] = std::min<int64_t>(mn[a], dm.coords[(size_t)a * dm.n + x]);
-            auto brick_of = [&](int64_t x) {
-                const uint64_t px = (uint64_t)(dm.coords[x] - mn[0]);
-                const uint64_t py = (uint64_t)(dm.coords[(size_t)dm.n + x] - mn[1]);
-                const uint64_t pz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] - mn[2]);
-                return ((pz >> bb) << 34) | ((py >> bb) << 17) | (px >> bb);
-            };
-            for (int64_t x = 0; x < dm.n; ++x) {
-                const int32_t k = cls[d][x];
-                if (k >= 0) continue;
-                const uint64_t px = (uint64_t)(dm.coords[x] - mn[0]);
-                const uint64_t py = (uint64_t)(dm.coords[(size_t)dm.n + x] - mn[1]);
-                const uint64_t pz = (uint64_t)(dm.coords[(size_t)2 * dm.n + x] - mn[2]);
-                const uint64_t bkey = brick_of(x);
-                const uint64_t lkey = ((pz & bm) << (2 * bb)) | ((py & bm) << bb) | (px & bm);
-                // near: every fluid upstream site in this brick and not an
-                // iolet site (iolet groups sit after all bricks, far away)
-                bool near = true;
-                for (int j = 1; j < Q && near; ++j) {
-                    const int32_t y = dm.nbr[(size_t)j * dm.n + x];
-                    if (y >= 0 && (brick_of(y) != bkey || cls[d][y] >= 0)) near = false;
-                }
-                const uint64_t cl = (k == -1) ? (near ? 0 : 1) : (near ? 2 : 3);
-                kv.push_back({(bkey << (3 * bb + 2)) | (cl << (3 * bb)) | lkey, x});
-            }
-            std::sort(kv.begin(), kv.end());
-            size_t m = 0;
-            while (m < kv.size()) {
-                const uint64_t grp = kv[m].first >> (3 * bb);  // brick and class
-                align_tile();
-                const int64_t st = pos;
-                while (m < kv.size() && (kv[m].first >> (3 * bb)) == grp) {
-                    dm.c2g[kv[m].second] = pos++;
-                    ++m;
-                }
-                static const int32_t tag_of[4] = {hl::K_NEAR, hl::K_BULK, hl::K_NEARWALL, hl::K_WALL};
-                c->ranges.push_back({st, pos - st, d, tag_of[grp & 3]});
-            }
-        }
-        c->NB = 0;
-    } else if (inter) {
-        // bulk and wall sites together, in one range per domain
-        for (int d = 0; d < D; ++d) {
-            for (auto &v : cls[d])
-                if (v == -2) v = -3;  // wall, placed with the bulk sites below
-            c->doms[d].c2g.assign(c->doms[d].n, -1);
-        }
-        for (int d = 0; d < D; ++d) {
-            auto &cd = cls[d];
-            std::vector<int32_t> saved = cd;
-            for (auto &v : cd)
-                if (v == -3) v = -1;
-            align_tile();
-            const int64_t st = pos;
-            place(d, -1, mb);
-            cd = saved;
-            if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_BULK, true});
-        }
-        c->NB = 0;
-        c->site_wall.assign(pos, 0);
-        for (int d = 0; d < D; ++d)
-            for (int64_t x = 0; x < c->doms[d].n; ++x)
-                if (cls[d][x] == -3) c->site_wall[c->doms[d].c2g[x]] = 1;
-        for (int d = 0; d < D; ++d)
-            for (auto &v : cls[d])
-                if (v == -3) v = -2;
-    } else {
-        for (int d = 0; d < D; ++d) {
-            c->doms[d].c2g.assign(c->doms[d].n, -1);
-            align_tile();
-            const int64_t st = pos;
-            if (place(d, -1, mb) > 0) c->ranges.push_back({st, pos - st, d, hl::K_BULK});
-        }
-        align_tile();
-        c->NB = pos;
-        for (int d = 0; d < D; ++d) {
-            align_tile();
-            const int64_t st = pos;
-            if (place(d, -2, mw) > 0) c->ranges.push_back({st, pos - st, d, hl::K_WALL});
-        }
-    }
-    align_tile();
-    c->IO0 = pos;
-    std::vector<int64_t> io_lo(io_count, 0), io_n(io_count, 0);
-    for (int d = 0; d < D; ++d) {
-        Domain &dm = c->doms[d];
-        for (int k = 0; k < dm.n_iolet; ++k) {
-            align_tile();
-            const int64_t st = pos;
-            place(d, k, mw);
-            io_lo[dm.io_base + k] = st;
-            io_n[dm.io_base + k] = pos - st;
-            if (pos > st) c->ranges.push_back({st, pos - st, d, hl::K_IOLET | ((dm.io_base + k) << hl::CLASS_BITS)});
-        }
-    }
-    align_tile();
-    c->N = pos;  // padded: every range starts, and N ends, on a whole tile
-    c->Npad = (c->N + hl::TILE - 1) / hl::TILE * hl::TILE;
-    c->Nb = c->N - c->NB;
-    c->Nio = c->N - c->IO0;
-    const int64_t N = c->N, NB = c->NB, Nb = c->Nb, Nio = c->Nio;
-
-    // pull table, wall fractions, inlet profile, wall normals
-    std::vector<int32_t> src((size_t)18 * N);
-    std::vector<float> bq((size_t)18 * std::max<int64_t>(Nb, 1), 0.5f);
-    std::vector<double> bphi(std::max<int64_t>(Nb, 1), 0.0), bnrm((size_t)3 * std::max<int64_t>(Nb, 1), 0.0);
-    c->hio.assign(io_count, hl::IoletDev{});
-    for (int d = 0; d < D; ++d) {
-        Domain &dm = c->doms[d];
-        for (int64_t x = 0; x < dm.n; ++x) {
-            const int64_t g = dm.c2g[x];
-            for (int j = 1; j < Q; ++j) {
-                const int32_t up = dm.nbr[(size_t)opp_h(j) * dm.n + x];
-                int32_t v;
-                if (up >= 0)
-                    v = (int32_t)dm.c2g[up];
-                else if (up == -1)
-                    v = -1;
-                else
-                    v = -2 - (dm.io_base + (-2 - up));
-                src[(size_t)(j - 1) * N + g] = v;
-            }
-        }
-        for (size_t e = 0; e < dm.q.size(); ++e) {
-            const int64_t g = dm.c2g[dm.q_site[e]];
-            const int j = opp_h(dm.q_dir[e]);
-            bq[(size_t)(j - 1) * Nb + (g - NB)] = dm.q[e];
-        }
-        std::vector<double> userw;
-        std::vector<char> has_user;
-        if (!dm.wn_site.empty()) {
-            userw.assign((size_t)3 * dm.n, 0.0);
-            has_user.assign(dm.n, 0);
-            const size_t nw = dm.wn_site.size();
-            for (size_t e = 0; e < nw; ++e) {
-                const int64_t x = dm.wn_site[e];
-                has_user[x] = 1;
-                for (int a = 0; a < 3; ++a) userw[(size_t)a * dm.n + x] = dm.wn[a * nw + e];
-            }
-        }
-        for (int64_t x = 0; x < dm.n; ++x) {
-            const int64_t g = dm.c2g[x];
-            if (g < NB) continue;
-            const int64_t b = g - NB;
-            double nv[3] = {0, 0, 0};
-            bool wall = false;
-            for (int i = 1; i < Q; ++i)
-                if (dm.nbr[(size_t)i * dm.n + x] == -1) {
-                    wall = true;
-                    nv[0] -= CXh[i];
-                    nv[1] -= CYh[i];
-                    nv[2] -= CZh[i];
-                }
-            if (wall) {
-                if (!has_user.empty() && has_user[x])
-                    for (int a = 0; a < 3; ++a) nv[a] = userw[(size_t)a * dm.n + x];
-                const double nl = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-                if (nl > 0.0)
-                    for (int a = 0; a < 3; ++a) bnrm[(size_t)a * Nb + b] = nv[a] / nl;
-            }
-            const int32_t k = cls[d][x];
-            if (k >= 0 && dm.io[k].kind == hl::KIND_INLET) {
-                const IoletH &io = dm.io[k];
-                double dv[3], dn = 0.0, dd = 0.0;
-                for (int a = 0; a < 3; ++a) {
-                    dv[a] = (double)dm.coords[(size_t)a * dm.n + x] - io.c[a];
-                    dn = dn + dv[a] * io.nrm[a];
-                    dd = dd + dv[a] * dv[a];
-                }
-                const double r2 = dd - dn * dn;
-                const double v = 1.0 - r2 / (io.R * io.R);
-                bphi[b] = v > 0.0 ? v : 0.0;
-            }
-        }
-        for (int k = 0; k < dm.n_iolet; ++k) {
-            const int g = dm.io_base + k;
-            hl::IoletDev &io = c->hio[g];
-            const IoletH &ih = dm.io[k];
-            for (int a = 0; a < 3; ++a) io.nrm[a] = ih.nrm[a];
-            io.area = (double)io_n[g];
-            double sp = 0.0;
-            for (int64_t s = io_lo[g]; s < io_lo[g] + io_n[g]; ++s) sp = sp + bphi[s - NB];
-            io.phibar = io_n[g] ? sp / (double)io_n[g] : 0.0;
-            io.a0 = ih.wave.a0;
-            io.nh = ih.wave.nh;
-            io.period = ih.wave.period;
-            for (int m = 0; m < hl::MAXH; ++m) {
-                io.a[m] = ih.wave.a[m];
-                io.b[m] = ih.wave.b[m];
-            }
-            io.kind = ih.kind;
-            io.coupled = ih.coupled ? 1 : 0;
-            io.seg = d;
-        }
-    }
-    // coupling pairs grouped by arterial outlet, call order kept
-    c->hpairs.clear();
-    {
-        std::vector<size_t> order(c->pairs.size());
-        for (size_t p = 0; p < order.size(); ++p) order[p] = p;
-        auto outg = [&](size_t p) { return c->doms[c->pairs[p].da].io_base + c->pairs[p].ka; };
-        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return outg(x) < outg(y); });
-        for (size_t p : order) {
-            const PairH &ph = c->pairs[p];
-            hl::PairDev pd;
-            pd.out_g = c->doms[ph.da].io_base + ph.ka;
-            pd.in_g = c->doms[ph.db].io_base + ph.kb;
-            pd.s = ph.s;
-            pd.delta = ph.delta;
-            hl::IoletDev &o = c->hio[pd.out_g];
-            if (o.pair_n == 0) o.pair_lo = (int32_t)c->hpairs.size();
-            o.pair_n++;
-            c->hpairs.push_back(pd);
-        }
-    }
-    // int16 pull deltas of the K_NEAR and K_NEARWALL groups (INT16_MIN for a
-    // wall link); a group with a delta beyond the int16 range falls back to
-    // the int32 table (K_BULK or K_WALL)
-    std::vector<int16_t> d16(src.size(), 0);
-    c->n_near_sites = 0;
-    for (Range &g : c->ranges) {
-        if (g.tag != hl::K_NEAR && g.tag != hl::K_NEARWALL) continue;
-        bool fits = true;
-        for (int j = 1; j < Q && fits; ++j)
-            for (int64_t s = g.start; s < g.start + g.count; ++s) {
-                const int32_t v = src[(size_t)(j - 1) * N + s];
-                const int64_t dl = (int64_t)v - s;
-                if (v < -1 || (v >= 0 && (dl < -32767 || dl > 32767))) {
-                    fits = false;
-                    break;
-                }
-                d16[(size_t)(j - 1) * N + s] = (v == -1) ? (int16_t)INT16_MIN : (int16_t)dl;
-            }
-        if (fits)
-            c->n_near_sites += g.count;
-        else
-            g.tag = (g.tag == hl::K_NEAR) ? hl::K_BULK : hl::K_WALL;
-    }
-    c->hseg.clear();
-    for (auto &d : c->doms) c->hseg.push_back(seg_of(d));
-    build_entries(c);
+    const int64_t Nio = c->L.Nio;
 
     // device memory
     const size_t S = store_bytes(c->precision), A = arith_bytes(c->precision);
-    int rc;
     for (int p = 0; p < 2; ++p) {
         if (p == 0 || !c->aa) {
-            HIPC(c, hipMalloc(&c->lat[p], (size_t)Q * c->Npad * S));
-            c->dev_bytes += (int64_t)((size_t)Q * c->Npad * S);
+            HIPC(c, hipMalloc(&c->lat[p], (size_t)Q * c->L.Npad * S));
+            c->dev_bytes += (int64_t)((size_t)Q * c->L.Npad * S);
         }
         HIPC(c, hipMalloc(&c->d_up[p], std::max<size_t>((size_t)3 * Nio * A, 8)));
         c->dev_bytes += (int64_t)std::max<size_t>((size_t)3 * Nio * A, 8);
     }
-    if ((rc = dalloc(c, &c->d_src, src.size())) != HL_OK) return rc;
-    if ((rc = dalloc(c, &c->d_d16, d16.size())) != HL_OK) return rc;
-    if ((rc = dalloc(c, &c->d_bq, bq.size())) != HL_OK) return rc;
-    if ((rc = dalloc(c, &c->d_bphi, bphi.size())) != HL_OK) return rc;
-    if ((rc = dalloc(c, &c->d_bnrm, bnrm.size())) != HL_OK) return rc;
-    if ((rc = dalloc(c, &c->d_seg, c->hseg.size())) != HL_OK) return rc;
-    if ((rc = dalloc(c, &c->d_io, c->hio.size())) != HL_OK) return rc;
-    if ((rc = dalloc(c, &c->d_pairs, c->hpairs.size())) != HL_OK) return rc;
+    const hl::Layout &L = c->L;
+    if ((rc = dalloc(c, &c->d_src, L.src.size())) != HL_OK) return rc;
+    if (!L.d16.empty() && (rc = dalloc(c, &c->d_d16, L.d16.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_bq, L.bq.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_bphi, L.bphi.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_bnrm, L.bnrm.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_seg, c->L.hseg.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_io, c->L.hio.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_pairs, c->L.hpairs.size())) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_ctrl, 1)) != HL_OK) return rc;
-    const size_t nio1 = std::max<size_t>(c->hio.size(), 1);
+    const size_t nio1 = std::max<size_t>(c->L.hio.size(), 1);
     if ((rc = dalloc(c, &c->d_stats, 2 * nio1)) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_bc, 2 * nio1)) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_held, nio1)) != HL_OK) return rc;
-    HIPC(c, hipMemcpy(c->d_src, src.data(), src.size() * 4, hipMemcpyHostToDevice));
-    HIPC(c, hipMemcpy(c->d_d16, d16.data(), d16.size() * 2, hipMemcpyHostToDevice));
-    HIPC(c, hipMemcpy(c->d_bq, bq.data(), bq.size() * 4, hipMemcpyHostToDevice));
-    HIPC(c, hipMemcpy(c->d_bphi, bphi.data(), bphi.size() * 8, hipMemcpyHostToDevice));
-    HIPC(c, hipMemcpy(c->d_bnrm, bnrm.data(), bnrm.size() * 8, hipMemcpyHostToDevice));
-    HIPC(c, hipMemcpy(c->d_seg, c->hseg.data(), c->hseg.size() * sizeof(hl::SegDev), hipMemcpyHostToDevice));
-    if (!c->hpairs.empty())
-        HIPC(c, hipMemcpy(c->d_pairs, c->hpairs.data(), c->hpairs.size() * sizeof(hl::PairDev),
+    HIPC(c, hipMemcpy(c->d_src, L.src.data(), L.src.size() * 4, hipMemcpyHostToDevice));
+    if (!L.d16.empty()) HIPC(c, hipMemcpy(c->d_d16, L.d16.data(), L.d16.size() * 2, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_bq, L.bq.data(), L.bq.size() * 4, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_bphi, L.bphi.data(), L.bphi.size() * 8, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_bnrm, L.bnrm.data(), L.bnrm.size() * 8, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_seg, c->L.hseg.data(), c->L.hseg.size() * sizeof(hl::SegDev), hipMemcpyHostToDevice));
+    if (!c->L.hpairs.empty())
+        HIPC(c, hipMemcpy(c->d_pairs, c->L.hpairs.data(), c->L.hpairs.size() * sizeof(hl::PairDev),
                           hipMemcpyHostToDevice));
     if ((rc = upload_schedule(c)) != HL_OK) return rc;
     std::vector<double> held(nio1, 0.0), zeros(2 * nio1, 0.0);
@@ -879,11 +427,16 @@ int commit(hl_ctx *c) {
     HIPC(c, hipMemcpy(c->d_stats, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice));
     hl::Ctrl ctrl{};
     HIPC(c, hipMemcpy(c->d_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
-    // geometry arrays are no longer needed on the host
+    // geometry arrays and uploaded tables are no longer needed on the host
     for (auto &d : c->doms) {
         std::vector<int32_t>().swap(d.nbr);
         std::vector<int32_t>().swap(d.coords);
     }
+    std::vector<int32_t>().swap(c->L.src);
+    std::vector<int16_t>().swap(c->L.d16);
+    std::vector<float>().swap(c->L.bq);
+    std::vector<double>().swap(c->L.bphi);
+    std::vector<double>().swap(c->L.bnrm);
     c->committed = true;
     c->t_host = 0;
     // initial state: rest equilibrium at rho0, collided into f*(0)
@@ -896,37 +449,9 @@ int commit(hl_ctx *c) {
 }
 
 int validate(hl_ctx *c, int64_t n, const int32_t *nbr, int64_t n_iolet) {
-    if (n < 0 || n > INT32_MAX) return fail(c, HL_E_RANGE, "site count %lld out of range", (long long)n);
-    if (n_iolet < 0 || n_iolet > (1 << 20)) return fail(c, HL_E_RANGE, "iolet count out of range");
-    if (n > 0 && !nbr) return fail(c, HL_E_INVAL, "nbr is NULL");
-    for (int64_t x = 0; x < n; ++x)
-        if (nbr[x] != x) return fail(c, HL_E_RANGE, "nbr[0][%lld] must equal the site index", (long long)x);
-    for (int i = 1; i < Q; ++i) {
-        const int32_t *row = nbr + (size_t)i * n;
-        const int32_t *back = nbr + (size_t)opp_h(i) * n;
-        for (int64_t x = 0; x < n; ++x) {
-            const int32_t v = row[x];
-            if (v >= 0) {
-                if (v >= n) return fail(c, HL_E_RANGE, "nbr[%d][%lld] = %d >= n", i, (long long)x, v);
-                if (back[v] != x)
-                    return fail(c, HL_E_INVAL, "link (%lld, %d) has no reverse link", (long long)x, i);
-            } else if (v < -1 - n_iolet) {
-                return fail(c, HL_E_RANGE, "nbr[%d][%lld] = %d is not a known code", i, (long long)x, v);
-            }
-        }
-    }
-    for (int64_t x = 0; x < n; ++x) {
-        int32_t k = 0;
-        for (int i = 1; i < Q; ++i) {
-            const int32_t v = nbr[(size_t)i * n + x];
-            if (v <= -2) {
-                if (k != 0 && k != v)
-                    return fail(c, HL_E_INVAL, "site %lld borders two iolets", (long long)x);
-                k = v;
-            }
-        }
-    }
-    return HL_OK;
+    std::string err;
+    const int rc = hl::validate_sites(n, nbr, n_iolet, err);
+    return rc == HL_OK ? HL_OK : fail(c, rc, "%s", err.c_str());
 }
 
 int parse_series(hl_ctx *c, Series &s, double a0, int nh, const double *a, const double *b, double period) {
@@ -953,9 +478,9 @@ struct StateHeader {
 
 size_t state_bytes(hl_ctx *c) {
     const size_t S = store_bytes(c->precision), A = arith_bytes(c->precision);
-    const size_t nio = c->hio.size();
+    const size_t nio = c->L.hio.size();
     const size_t nlat = c->aa ? 1 : 2;
-    return sizeof(StateHeader) + sizeof(hl::Ctrl) + nlat * (size_t)Q * c->Npad * S + 2 * (size_t)3 * c->Nio * A +
+    return sizeof(StateHeader) + sizeof(hl::Ctrl) + nlat * (size_t)Q * c->L.Npad * S + 2 * (size_t)3 * c->L.Nio * A +
            (2 + 2 + 1) * nio * sizeof(double);
 }
 
@@ -988,7 +513,7 @@ int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     *out = nullptr;
     if (precision < HL_F64 || precision > HL_F16_STOCHASTIC) return HL_E_INVAL;
     if (flags & ~(uint64_t)(HL_ORDER_BULK_MORTON | HL_ORDER_BOUNDARY_MORTON | HL_ORDER_INTERLEAVE | HL_ORDER_BRICK |
-                            HL_SCHEME_AA | HL_ORDER_BRICK_32))
+                            HL_SCHEME_AA | HL_ORDER_BRICK_32 | HL_DEBUG_CHECKS))
         return HL_E_INVAL;
     if ((flags & HL_ORDER_BRICK_32) && !(flags & HL_ORDER_BRICK)) return HL_E_INVAL;
     int count = 0;
@@ -1002,6 +527,7 @@ int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     c->precision = precision;
     c->order_flags = flags;
     c->aa = (flags & HL_SCHEME_AA) != 0;
+    c->debug_checks = (flags & HL_DEBUG_CHECKS) != 0;
     if (hipHostMalloc((void **)&c->h_nan, sizeof(int), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return HL_E_NOMEM;
@@ -1023,7 +549,15 @@ void hl_destroy(hl_ctx *ctx) {
 
 int hl_set_stream(hl_ctx *ctx, void *hip_stream) {
     if (!ctx) return HL_E_INVAL;
-    ctx->stream = (hipStream_t)hip_stream;
+    hipStream_t next = (hipStream_t)hip_stream;
+    if (next == ctx->stream) return HL_OK;
+    // work queued on the old stream finishes before anything is queued on the
+    // new one (later reads, steps and hl_destroy wait on the new stream only)
+    if (ctx->committed) {
+        HIPC(ctx, hipSetDevice(ctx->device));
+        HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    ctx->stream = next;
     return HL_OK;
 }
 
@@ -1228,7 +762,7 @@ static int read_component(hl_ctx *ctx, int32_t dom, int comp, int ncomp, double 
     if ((rc = commit(ctx)) != HL_OK) return rc;
     HIPC(ctx, hipSetDevice(ctx->device));
     if ((rc = observe(ctx, false)) != HL_OK) return rc;
-    const int64_t N = ctx->N;
+    const int64_t N = ctx->L.N;
     std::vector<double> buf((size_t)ncomp * N);
     HIPC(ctx, hipMemcpyAsync(buf.data(), ctx->d_obs + (size_t)comp * N, buf.size() * 8, hipMemcpyDeviceToHost,
                              ctx->stream));
@@ -1250,7 +784,7 @@ int hl_read_populations(hl_ctx *ctx, int32_t dom, double *out) {
     if ((rc = commit(ctx)) != HL_OK) return rc;
     HIPC(ctx, hipSetDevice(ctx->device));
     if ((rc = observe(ctx, true)) != HL_OK) return rc;
-    const int64_t N = ctx->N;
+    const int64_t N = ctx->L.N;
     std::vector<double> buf((size_t)Q * N);
     HIPC(ctx, hipMemcpyAsync(buf.data(), ctx->d_fbuf, buf.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
@@ -1267,7 +801,7 @@ int hl_set_populations(hl_ctx *ctx, int32_t dom, const double *f) {
     if ((rc = commit(ctx)) != HL_OK) return rc;
     HIPC(ctx, hipSetDevice(ctx->device));
     if ((rc = observe(ctx, true)) != HL_OK) return rc;
-    const int64_t N = ctx->N;
+    const int64_t N = ctx->L.N;
     std::vector<double> buf((size_t)Q * N);
     HIPC(ctx, hipMemcpyAsync(buf.data(), ctx->d_fbuf, buf.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
@@ -1281,7 +815,7 @@ int hl_set_populations(hl_ctx *ctx, int32_t dom, const double *f) {
     hl::KArgs a = make_args(ctx);
     a.fin = ctx->d_fbuf;
     int e = (ctx->aa && (ctx->t_host & 1))
-                ? hl::launch_aa_load_odd(ctx->precision, a, (int)ctx->entries.size(), ctx->block, ctx->stream)
+                ? hl::launch_aa_load_odd(ctx->precision, a, (int)ctx->L.entries.size(), ctx->block, ctx->stream)
                 : hl::launch_load_raw(ctx->precision, a, ctx->stream);
     if (e != 0) return fail(ctx, HL_E_DEVICE, "load launch failed: %s", hipGetErrorString((hipError_t)e));
     if ((rc = reinit(ctx)) != HL_OK) return rc;
@@ -1298,7 +832,7 @@ int hl_read_iolet_stats(hl_ctx *ctx, int32_t dom, double *mean_u, double *mean_p
     if (!mean_u || !mean_p) return fail(ctx, HL_E_INVAL, "NULL output");
     HIPC(ctx, hipSetDevice(ctx->device));
     if (ctx->aa && (rc = ensure_stats(ctx)) != HL_OK) return rc;
-    const size_t nio = ctx->hio.size();
+    const size_t nio = ctx->L.hio.size();
     std::vector<double> st(2 * nio);
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     HIPC(ctx, hipMemcpy(st.data(), ctx->d_stats, st.size() * 8, hipMemcpyDeviceToHost));
@@ -1320,7 +854,7 @@ int hl_read_iolet_bc(hl_ctx *ctx, int32_t dom, int which, double *out) {
     if (!out) return fail(ctx, HL_E_INVAL, "NULL output");
     HIPC(ctx, hipSetDevice(ctx->device));
     if (ctx->aa && which == 0 && (rc = ensure_stats(ctx)) != HL_OK) return rc;
-    const size_t nio = ctx->hio.size();
+    const size_t nio = ctx->L.hio.size();
     std::vector<double> bc(2 * nio);
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     HIPC(ctx, hipMemcpy(bc.data(), ctx->d_bc, bc.size() * 8, hipMemcpyDeviceToHost));
@@ -1337,12 +871,13 @@ static int read_device(hl_ctx *ctx, int32_t dom, int comp, int ncomp, void *dptr
     HIPC(ctx, hipSetDevice(ctx->device));
     if ((rc = observe(ctx, false)) != HL_OK) return rc;
     Domain &d = ctx->doms[dom];
-    if (!d.d_c2g) {
-        if ((rc = dalloc(ctx, &d.d_c2g, d.n)) != HL_OK) return rc;
-        HIPC(ctx, hipMemcpy(d.d_c2g, d.c2g.data(), d.n * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (ctx->d_c2g.size() != ctx->doms.size()) ctx->d_c2g.assign(ctx->doms.size(), nullptr);
+    if (!ctx->d_c2g[dom]) {
+        if ((rc = dalloc(ctx, &ctx->d_c2g[dom], d.n)) != HL_OK) return rc;
+        HIPC(ctx, hipMemcpy(ctx->d_c2g[dom], d.c2g.data(), d.n * sizeof(int64_t), hipMemcpyHostToDevice));
     }
     for (int m = 0; m < ncomp; ++m) {
-        int e = hl::launch_gather_obs(ctx->d_obs + (size_t)(comp + m) * ctx->N, d.d_c2g, d.n,
+        int e = hl::launch_gather_obs(ctx->d_obs + (size_t)(comp + m) * ctx->L.N, ctx->d_c2g[dom], d.n,
                                       (double *)dptr + (size_t)m * d.n, ctx->stream);
         if (e != 0) return fail(ctx, HL_E_DEVICE, "gather launch failed");
     }
@@ -1371,22 +906,22 @@ int hl_get_state(hl_ctx *ctx, void *buf, size_t *bytes) {
     std::memcpy(h.magic, "HLSTATE", 8);
     h.version = 1;
     h.precision = ctx->precision | (ctx->aa ? 0x100 : 0);
-    h.N = ctx->N;
-    h.Nio = ctx->Nio;
-    h.n_io = (int64_t)ctx->hio.size();
+    h.N = ctx->L.N;
+    h.Nio = ctx->L.Nio;
+    h.n_io = (int64_t)ctx->L.hio.size();
     h.bytes = (int64_t)need;
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
-    const size_t S = store_bytes(ctx->precision), A = arith_bytes(ctx->precision), nio = ctx->hio.size();
+    const size_t S = store_bytes(ctx->precision), A = arith_bytes(ctx->precision), nio = ctx->L.hio.size();
     HIPC(ctx, hipMemcpy(p, ctx->d_ctrl, sizeof(hl::Ctrl), hipMemcpyDeviceToHost));
     p += sizeof(hl::Ctrl);
     for (int k = 0; k < (ctx->aa ? 1 : 2); ++k) {
-        HIPC(ctx, hipMemcpy(p, ctx->lat[k], (size_t)Q * ctx->Npad * S, hipMemcpyDeviceToHost));
-        p += (size_t)Q * ctx->Npad * S;
+        HIPC(ctx, hipMemcpy(p, ctx->lat[k], (size_t)Q * ctx->L.Npad * S, hipMemcpyDeviceToHost));
+        p += (size_t)Q * ctx->L.Npad * S;
     }
     for (int k = 0; k < 2; ++k) {
-        if (ctx->Nio) HIPC(ctx, hipMemcpy(p, ctx->d_up[k], (size_t)3 * ctx->Nio * A, hipMemcpyDeviceToHost));
-        p += (size_t)3 * ctx->Nio * A;
+        if (ctx->L.Nio) HIPC(ctx, hipMemcpy(p, ctx->d_up[k], (size_t)3 * ctx->L.Nio * A, hipMemcpyDeviceToHost));
+        p += (size_t)3 * ctx->L.Nio * A;
     }
     if (nio) {
         HIPC(ctx, hipMemcpy(p, ctx->d_stats, 2 * nio * 8, hipMemcpyDeviceToHost));
@@ -1407,24 +942,24 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes) {
     if (std::memcmp(h.magic, "HLSTATE", 8) != 0 || h.version != 1)
         return fail(ctx, HL_E_INVAL, "not a state buffer of this library version");
     if (bytes != need || h.bytes != (int64_t)need || h.precision != (ctx->precision | (ctx->aa ? 0x100 : 0)) ||
-        h.N != ctx->N ||
-        h.Nio != ctx->Nio || h.n_io != (int64_t)ctx->hio.size())
+        h.N != ctx->L.N ||
+        h.Nio != ctx->L.Nio || h.n_io != (int64_t)ctx->L.hio.size())
         return fail(ctx, HL_E_INVAL, "state layout does not match this context");
     HIPC(ctx, hipSetDevice(ctx->device));
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     const char *p = (const char *)buf + sizeof h;
-    const size_t S = store_bytes(ctx->precision), A = arith_bytes(ctx->precision), nio = ctx->hio.size();
+    const size_t S = store_bytes(ctx->precision), A = arith_bytes(ctx->precision), nio = ctx->L.hio.size();
     hl::Ctrl ctrl;
     std::memcpy(&ctrl, p, sizeof ctrl);
     HIPC(ctx, hipMemcpy(ctx->d_ctrl, &ctrl, sizeof ctrl, hipMemcpyHostToDevice));
     p += sizeof(hl::Ctrl);
     for (int k = 0; k < (ctx->aa ? 1 : 2); ++k) {
-        HIPC(ctx, hipMemcpy(ctx->lat[k], p, (size_t)Q * ctx->Npad * S, hipMemcpyHostToDevice));
-        p += (size_t)Q * ctx->Npad * S;
+        HIPC(ctx, hipMemcpy(ctx->lat[k], p, (size_t)Q * ctx->L.Npad * S, hipMemcpyHostToDevice));
+        p += (size_t)Q * ctx->L.Npad * S;
     }
     for (int k = 0; k < 2; ++k) {
-        if (ctx->Nio) HIPC(ctx, hipMemcpy(ctx->d_up[k], p, (size_t)3 * ctx->Nio * A, hipMemcpyHostToDevice));
-        p += (size_t)3 * ctx->Nio * A;
+        if (ctx->L.Nio) HIPC(ctx, hipMemcpy(ctx->d_up[k], p, (size_t)3 * ctx->L.Nio * A, hipMemcpyHostToDevice));
+        p += (size_t)3 * ctx->L.Nio * A;
     }
     if (nio) {
         HIPC(ctx, hipMemcpy(ctx->d_stats, p, 2 * nio * 8, hipMemcpyHostToDevice));
@@ -1449,18 +984,24 @@ int hl_set_schedule(hl_ctx *ctx, int32_t block_size, int32_t flags) {
     if (!ctx) return HL_E_INVAL;
     if (block_size != 64 && block_size != 128 && block_size != 256)
         return fail(ctx, HL_E_INVAL, "block size %d not in {64, 128, 256}", block_size);
-    if (flags & ~(int32_t)(HL_SCHED_XCD_REMAP | HL_SCHED_FUSED | HL_SCHED_PAIRS | HL_SCHED_XCD_RUNS))
+    if (flags & ~(int32_t)(HL_SCHED_XCD_REMAP | HL_SCHED_FUSED | HL_SCHED_PAIRS | HL_SCHED_XCD_RUNS |
+                           HL_SCHED_XCD_BRICKS))
         return fail(ctx, HL_E_INVAL, "unknown schedule flags");
     if ((flags & HL_SCHED_XCD_RUNS) && !(flags & HL_SCHED_XCD_REMAP))
         return fail(ctx, HL_E_INVAL, "HL_SCHED_XCD_RUNS needs HL_SCHED_XCD_REMAP");
-    const bool rebuild = block_size != ctx->block || ((flags ^ ctx->sched_flags) & HL_SCHED_FUSED);
+    if ((flags & HL_SCHED_XCD_BRICKS) &&
+        (!(flags & HL_SCHED_FUSED) || (flags & (HL_SCHED_XCD_REMAP | HL_SCHED_XCD_RUNS)) ||
+         !(ctx->order_flags & HL_ORDER_BRICK)))
+        return fail(ctx, HL_E_INVAL, "HL_SCHED_XCD_BRICKS needs HL_SCHED_FUSED alone and a brick layout");
+    const bool rebuild = block_size != ctx->block ||
+                         ((flags ^ ctx->sched_flags) & (HL_SCHED_FUSED | HL_SCHED_XCD_BRICKS));
     ctx->block = block_size;
     ctx->sched_flags = flags;
     if (!ctx->committed) return HL_OK;
     HIPC(ctx, hipSetDevice(ctx->device));
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     if (rebuild) {
-        build_entries(ctx);
+        hl::plan_schedule(ctx->L, ctx->block, ctx->sched_flags);
         return upload_schedule(ctx);
     }
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
@@ -1479,58 +1020,133 @@ int hl_autotune(hl_ctx *ctx, int budget_ms) {
     if ((rc = hl_get_state(ctx, nullptr, &bytes)) != HL_OK) return rc;
     std::vector<char> saved(bytes);
     if ((rc = hl_get_state(ctx, saved.data(), &bytes)) != HL_OK) return rc;
-    // the caller's drive comes back and the events go away on every exit
+    // On every exit the caller's drive comes back, the events go away and,
+    // unless a schedule was chosen, the caller's schedule and dynamic state
+    // are restored (a failing trial leaves nothing behind).
     struct Guard {
         hl_ctx *c;
-        int drive;
+        int drive, block, flags;
+        const std::vector<char> *state;
+        bool done = false;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         ~Guard() {
             if (e0) (void)hipEventDestroy(e0);
             if (e1) (void)hipEventDestroy(e1);
             c->drive = drive;
+            if (!done) {
+                const std::string err = c->err;  // keep the message of the failure
+                (void)hl_set_schedule(c, block, flags);
+                (void)hl_set_state(c, state->data(), state->size());
+                c->err = err;
+            }
         }
-    } guard{ctx, ctx->drive};
+    } guard{ctx, ctx->drive, ctx->block, ctx->sched_flags, &saved};
     ctx->drive = HL_DRIVE_LAUNCH;
     struct Cand { int block, flags; double ms; };
     std::vector<Cand> cands;
     const bool pairs_ok = !ctx->aa && ctx->precision != hl::PREC_F16W && ctx->precision != hl::PREC_F16SR;
+    const bool bricks = (ctx->order_flags & HL_ORDER_BRICK) != 0;
     const int R1 = (int)HL_SCHED_XCD_REMAP, RR = (int)(HL_SCHED_XCD_REMAP | HL_SCHED_XCD_RUNS);
-    const int F = (int)HL_SCHED_FUSED, P = (int)HL_SCHED_PAIRS;
-    for (int b : {64, 128, 256})
+    const int F = (int)HL_SCHED_FUSED, P = (int)HL_SCHED_PAIRS, B = (int)HL_SCHED_XCD_BRICKS;
+    for (int b : {64, 128, 256}) {
         for (int f : {0, R1, RR, F, F | R1, F | RR, P, P | R1, P | RR})
             if (pairs_ok || !(f & HL_SCHED_PAIRS)) cands.push_back({b, f, 0.0});
+        if (bricks) cands.push_back({b, F | B, 0.0});
+    }
     HIPC(ctx, hipEventCreate(&guard.e0));
     HIPC(ctx, hipEventCreate(&guard.e1));
     hipEvent_t e0 = guard.e0, e1 = guard.e1;
-    // steps per candidate from one timed step of the current schedule
-    int64_t reps = 2;
-    {
-        if ((rc = run_steps(ctx, 1)) != HL_OK) return rc;
+    auto time_steps = [&](int64_t n, double *ms_per_step) -> int {
+        int r;
+        if ((r = run_steps(ctx, 1)) != HL_OK) return r;
         HIPC(ctx, hipEventRecord(e0, ctx->stream));
-        if ((rc = run_steps(ctx, 2)) != HL_OK) return rc;
+        if ((r = run_steps(ctx, n)) != HL_OK) return r;
         HIPC(ctx, hipEventRecord(e1, ctx->stream));
         HIPC(ctx, hipEventSynchronize(e1));
         float ms = 0.0f;
         HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
-        const double per = std::max(1e-3, (double)ms / 2.0);
-        reps = std::max<int64_t>(2, (int64_t)((double)budget_ms / (per * (double)cands.size())));
+        *ms_per_step = (double)ms / (double)n;
+        return HL_OK;
+    };
+    // steps per trial from two timed steps of the current schedule: 60 % of
+    // the budget for one trial of every candidate, 40 % for five more trials
+    // of the three fastest
+    constexpr int REPEAT = 5, TOP = 3;
+    int64_t reps = 2;
+    {
+        double per = 0.0;
+        if ((rc = time_steps(2, &per)) != HL_OK) return rc;
+        per = std::max(1e-3, per);
+        const double trials = (double)cands.size() / 0.6;
+        reps = std::max<int64_t>(2, (int64_t)((double)budget_ms / (per * trials)));
         reps = std::min<int64_t>(reps, 200);
     }
     for (auto &cd : cands) {
         if ((rc = hl_set_schedule(ctx, cd.block, cd.flags)) != HL_OK) return rc;
-        if ((rc = run_steps(ctx, 1)) != HL_OK) return rc;
-        HIPC(ctx, hipEventRecord(e0, ctx->stream));
-        if ((rc = run_steps(ctx, reps)) != HL_OK) return rc;
-        HIPC(ctx, hipEventRecord(e1, ctx->stream));
-        HIPC(ctx, hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
-        cd.ms = (double)ms / (double)reps;
+        if ((rc = time_steps(reps, &cd.ms)) != HL_OK) return rc;
     }
-    const Cand best = *std::min_element(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
-    if ((rc = hl_set_schedule(ctx, best.block, best.flags)) != HL_OK) return rc;
-    ctx->drive = guard.drive;
-    return hl_set_state(ctx, saved.data(), saved.size());
+    std::vector<Cand> top = cands;
+    std::sort(top.begin(), top.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
+    top.resize(std::min<size_t>(top.size(), TOP));
+    std::vector<std::vector<double>> runs(top.size());
+    for (int r = 0; r < REPEAT; ++r)
+        for (size_t k = 0; k < top.size(); ++k) {  // interleaved, so a slow spell hits all three
+            if ((rc = hl_set_schedule(ctx, top[k].block, top[k].flags)) != HL_OK) return rc;
+            double ms = 0.0;
+            if ((rc = time_steps(reps, &ms)) != HL_OK) return rc;
+            runs[k].push_back(ms);
+        }
+    std::vector<double> med(top.size());
+    for (size_t k = 0; k < top.size(); ++k) {
+        std::vector<double> v = runs[k];
+        std::sort(v.begin(), v.end());
+        med[k] = v[v.size() / 2];
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < top.size(); ++k)
+        if (med[k] < med[best]) best = k;
+    if ((rc = hl_set_schedule(ctx, top[best].block, top[best].flags)) != HL_OK) return rc;
+    if ((rc = hl_set_state(ctx, saved.data(), saved.size())) != HL_OK) return rc;
+    guard.done = true;
+    const auto mm = std::minmax_element(runs[best].begin(), runs[best].end());
+    ctx->tune_n = (int32_t)cands.size();
+    ctx->tune_best = med[best];
+    ctx->tune_second = med[best];
+    bool second = false;
+    for (size_t k = 0; k < top.size(); ++k)
+        if (k != best && (!second || med[k] < ctx->tune_second)) {
+            ctx->tune_second = med[k];
+            second = true;
+        }
+    ctx->tune_spread = med[best] > 0.0 ? (*mm.second - *mm.first) / med[best] : 0.0;
+    return HL_OK;
+}
+
+int hl_autotune_report(hl_ctx *ctx, int32_t *n_candidates, double *best_ms, double *runner_up_ms, double *spread) {
+    if (!ctx || !n_candidates || !best_ms || !runner_up_ms || !spread) return HL_E_INVAL;
+    if (ctx->tune_n == 0) return fail(ctx, HL_E_STATE, "no autotuning has run on this context");
+    *n_candidates = ctx->tune_n;
+    *best_ms = ctx->tune_best;
+    *runner_up_ms = ctx->tune_second;
+    *spread = ctx->tune_spread;
+    return HL_OK;
+}
+
+int hl_coupling_map(int32_t n_out, const double *out_c, int32_t n_in, const double *in_c, int32_t *owner,
+                    double *dist) {
+    if (n_out < 1 || n_in < 0 || !out_c || (n_in > 0 && (!in_c || !owner || !dist))) return HL_E_INVAL;
+    hl::coupling_map(n_out, out_c, n_in, in_c, owner, dist);
+    return HL_OK;
+}
+
+int hl_velocity_factors(int32_t nv, const double *dp, const double *L, const double *A, double A0, double *v) {
+    if (nv < 1 || !dp || !L || !A || !v || !(A0 > 0.0) || !std::isfinite(A0)) return HL_E_INVAL;
+    for (int32_t i = 0; i < nv; ++i)
+        if (!(dp[i] > 0.0) || !(L[i] > 0.0) || !(A[i] > 0.0) || !std::isfinite(dp[i]) || !std::isfinite(L[i]) ||
+            !std::isfinite(A[i]))
+            return HL_E_INVAL;
+    hl::velocity_factors(nv, dp, L, A, A0, v);
+    return HL_OK;
 }
 
 int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd) {
@@ -1547,9 +1163,9 @@ int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd
     int err = 0;
     auto part = [&](int64_t k, int which) {
         const int odd = (int)((ctx->t_host + k) & 1);
-        return ctx->aa ? hl::launch_aa_step(ctx->precision, a, ctx->n_bulk_blocks, ctx->n_bnd_blocks, ctx->block,
+        return ctx->aa ? hl::launch_aa_step(ctx->precision, a, ctx->L.n_bulk_blocks, ctx->L.n_bnd_blocks, ctx->block,
                                             ctx->stream, which, fu, odd)
-                       : hl::launch_step(ctx->precision, a, ctx->n_bulk_blocks, ctx->n_bnd_blocks, ctx->block,
+                       : hl::launch_step(ctx->precision, a, ctx->L.n_bulk_blocks, ctx->L.n_bnd_blocks, ctx->block,
                                          ctx->stream, which, fu);
     };
     for (int64_t k = 0; k < nsteps && !err; ++k) {
@@ -1584,15 +1200,15 @@ int hl_get_info(hl_ctx *ctx, hl_info *out) {
     int rc = commit(ctx);
     if (rc) return rc;
     std::memset(out, 0, sizeof *out);
-    out->n_sites = ctx->n_sites;
-    out->n_bulk = ctx->n_bulk_sites;
-    out->n_near = ctx->n_near_sites;
-    out->n_boundary = ctx->n_sites - ctx->n_bulk_sites;
-    out->n_iolet_sites = ctx->n_io_sites;
+    out->n_sites = ctx->L.n_sites;
+    out->n_bulk = ctx->L.n_bulk_sites;
+    out->n_near = ctx->L.n_near_sites;
+    out->n_boundary = ctx->L.n_sites - ctx->L.n_bulk_sites;
+    out->n_iolet_sites = ctx->L.n_io_sites;
     out->n_domains = (int32_t)ctx->doms.size();
-    out->n_iolets = (int32_t)ctx->hio.size();
-    out->n_blocks_bulk = ctx->n_bulk_blocks;
-    out->n_blocks_bnd = ctx->n_bnd_blocks;
+    out->n_iolets = (int32_t)ctx->L.hio.size();
+    out->n_blocks_bulk = ctx->L.n_bulk_blocks;
+    out->n_blocks_bnd = ctx->L.n_bnd_blocks;
     out->precision = ctx->precision;
     out->block_size = ctx->block;
     out->sched_flags = ctx->sched_flags;

@@ -35,8 +35,9 @@ constexpr double RHO0 = 1.0;
 // do (int16 deltas, INT16_MIN for a wall link, K_NEARWALL).
 enum : int32_t { K_BULK = 0, K_WALL = 1, K_IOLET = 2, K_NEAR = 3, K_NEARWALL = 4 };
 constexpr int CLASS_BITS = 3;
-__host__ __device__ inline int tag_class(int32_t tag) { return tag & ((1 << CLASS_BITS) - 1); }
-__host__ __device__ inline int tag_iolet(int32_t tag) { return tag >> CLASS_BITS; }
+// (constexpr: usable in host code built without HIP and in device code)
+constexpr int tag_class(int32_t tag) { return tag & ((1 << CLASS_BITS) - 1); }
+constexpr int tag_iolet(int32_t tag) { return tag >> CLASS_BITS; }
 enum : int32_t { KIND_INLET = 0, KIND_OUTLET = 1 };
 enum : int32_t { WALL_SBB = 0, WALL_BOUZIDI = 1 };
 enum : int32_t { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1 };
@@ -103,6 +104,8 @@ struct KArgs {
     int32_t aa;              // 1: one in-place lattice (lat0), AA-pattern sweeps
     int32_t n_pairs_blocks;  // > 0: the bulk launch runs the two-sites-per-lane kernel
     int32_t io_e0, io_e1;    // entry span covering every iolet's entries (empty: io_e0 == io_e1)
+    const int32_t *emap;     // brick-aligned XCD order of the fused launch: work-group b takes entry
+    int32_t n_emap;          // emap[b] (nothing when < 0); n_emap work-groups (null: storage order)
     Ctrl *ctrl;
     double *partials;  // [2][n_entries]
     double *stats;     // [2][n_io]: mean u.n, mean rho

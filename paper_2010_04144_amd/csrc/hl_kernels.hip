@@ -200,6 +200,13 @@ __device__ __forceinline__ int block_index(int xcd_remap) {
     return ((k / C) * 8 + x) * C + (k % C);
 }
 
+// Entry of this work-group: from the brick-aligned XCD map when the host
+// built one (negative: no work), else through block_index.
+__device__ __forceinline__ int entry_index(const KArgs &a) {
+    if (a.emap) return a.emap[blockIdx.x];
+    return a.e_off + block_index(a.xcd_remap);
+}
+
 // ---------------------------------------------------------------------------
 // Step 1-2: the populations f_j(x, p+1) of site s, streamed from f*(p).
 // BND selects the boundary path (pull codes may be negative).
@@ -476,7 +483,8 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
     __shared__ double lds[8];
     const int64_t t = a.ctrl->t;
     const int64_t tn = (MODE == M_RAW) ? t : t + 1;
-    const int eidx = a.e_off + block_index(a.xcd_remap);
+    const int eidx = entry_index(a);
+    if (eidx < 0) return;  // uniform over the work-group
     const Entry e = a.entries[eidx];
     const int klass = tag_class(e.tag);
     const SegDev &sg = a.seg[e.seg];
@@ -625,11 +633,21 @@ __global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
         x0[0] = ldc(lin + lidx(0, s), 0);
         x1[0] = R(0);
     }
+    const bool near = tag_class(e.tag) == K_NEAR;
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
         const int32_t *sp = a.src + (size_t)(j - 1) * N + s;
+        const int16_t *dp = near ? a.d16 + (size_t)(j - 1) * N + s : nullptr;
         if (two) {
-            const int2v sv = *(const int2v *)sp;
+            int2v sv;
+            if (near) {
+                // the two int16 deltas of sites s, s+1 as one aligned dword (s and N even)
+                const uint32_t pk = *(const uint32_t *)dp;
+                sv.x = (int32_t)s + (int32_t)(int16_t)(uint16_t)(pk & 0xffffu);
+                sv.y = (int32_t)s + 1 + (int32_t)(int16_t)(uint16_t)(pk >> 16);
+            } else {
+                sv = *(const int2v *)sp;
+            }
             if (sv.y == sv.x + 1 && (sv.x & (TILE - 1)) != TILE - 1) {
                 // adjacent sources in one tile: one vector load
                 V2 v;
@@ -641,7 +659,7 @@ __global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
                 x1[j] = ldc(lin + lidx(j, sv.y), j);
             }
         } else {
-            x0[j] = ldc(lin + lidx(j, sp[0]), j);
+            x0[j] = ldc(lin + lidx(j, near ? (int32_t)s + (int32_t)dp[0] : sp[0]), j);
             x1[j] = R(0);
         }
     }
@@ -867,7 +885,8 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     __shared__ double lds[8];
     const int64_t t = a.ctrl->t;
     const int direct = a.ctrl->direct;
-    const int eidx = a.e_off + block_index(a.xcd_remap);
+    const int eidx = entry_index(a);
+    if (eidx < 0) return;  // uniform over the work-group
     const Entry e = a.entries[eidx];
     const int klass = tag_class(e.tag);
     const SegDev &sg = a.seg[e.seg];
@@ -1148,7 +1167,7 @@ static int step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStream_t
     KArgs a = a0;
     if (fused) {
         a.e_off = 0;
-        if ((part == 0 || part == 2) && n_bnd > 0) launch_mode<T, M_FUSED>(n_bnd, block, st, a);
+        if ((part == 0 || part == 2) && n_bnd > 0) launch_mode<T, M_FUSED>(a.emap ? a.n_emap : n_bnd, block, st, a);
     } else {
         if (n_bulk > 0 && (part == 0 || part == 1)) {
             a.e_off = 0;
@@ -1224,7 +1243,8 @@ static int aa_step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStrea
     KArgs a = a0;
     if (fused) {
         a.e_off = 0;
-        if ((part == 0 || part == 2) && n_bnd > 0) launch_aa_mode<T, M_FUSED, ODD>(n_bnd, block, st, a);
+        if ((part == 0 || part == 2) && n_bnd > 0)
+            launch_aa_mode<T, M_FUSED, ODD>(a.emap ? a.n_emap : n_bnd, block, st, a);
     } else {
         if (n_bulk > 0 && (part == 0 || part == 1)) {
             a.e_off = 0;

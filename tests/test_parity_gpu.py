@@ -280,14 +280,67 @@ def test_device_reads_match_host_reads(hl):
 
 
 def test_autotune_keeps_state(hl):
-    a = build_gpu(cylinder_scenario(nz=24), hl)
+    """The autotuner restores the dynamic state, keeps one of its candidates
+    and reports the three-finalist median timing and its spread."""
+    a = build_gpu(cylinder_scenario(nz=24), hl, order=hl.HL_ORDER_BRICK)
+    with pytest.raises(hl.HLError) as ei:
+        a.autotune_report()
+    assert ei.value.code == hl.HL_E_STATE
     a.step(10)
     before = a.populations(0)
-    a.autotune(50)
+    a.autotune(80)
     assert a.t == 10
     assert np.array_equal(a.populations(0), before)
     blk, flags = a.schedule()
     assert blk in (64, 128, 256)
+    n, best, second, spread = a.autotune_report()
+    assert n == 30                      # 3 sizes x (9 + the brick-aligned XCD runs)
+    assert 0.0 < best <= second and spread >= 0.0
+    a.step(5)
+    b = build_gpu(cylinder_scenario(nz=24), hl, order=hl.HL_ORDER_BRICK)
+    b.step(15)
+    assert np.array_equal(a.populations(0), b.populations(0))
+
+
+def test_stream_switch_orders_work(hl):
+    """Steps queued on one stream, then more after switching the context to
+    another stream: the result is bit for bit that of one stream (the switch
+    waits for the first stream's work)."""
+    import torch
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = build_gpu(cylinder_scenario(nz=16), hl)
+    a.commit()
+    a.set_stream(s1)
+    a.step(37)
+    a.set_stream(s2)
+    a.step(23)
+    fa = a.populations(0)
+    a.set_stream(None)
+    a.close()
+    b = build_gpu(cylinder_scenario(nz=16), hl)
+    b.step(60)
+    assert np.array_equal(fa, b.populations(0))
+
+
+@pytest.mark.parametrize("order", [8 | 32, 8, 8 | 16])
+def test_xcd_bricks_schedule(hl, oracle_mod, order):
+    """Brick-aligned XCD runs (fused launch through the host-built work-group
+    map, 64-site work-groups so a tree of about 100k sites gives many runs and
+    uneven XCD shares): FP64 matches the oracle in the two-lattice and the
+    in-place scheme; the layout is also checked exhaustively on the host
+    before the upload (HL_DEBUG_CHECKS)."""
+    geo = synth.tree_geometry(4, 10.0, 20100416, lam=6.0)
+    outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}
+    sc = Scenario([Dom(geo, tau=0.6, bouzidi=True, inlets={0: (0.01, (), (), 1.0)}, outlets=outs)])
+    o = build_oracle(sc, oracle_mod)
+    g = build_gpu(sc, hl, "f64", order=order | hl.HL_DEBUG_CHECKS)
+    g.set_schedule(64, hl.HL_SCHED_FUSED | hl.HL_SCHED_XCD_BRICKS)
+    o.step(101)
+    g.step(101)
+    check64(errors(g, o))
+    with pytest.raises(hl.HLError) as ei:
+        g.set_schedule(64, hl.HL_SCHED_XCD_BRICKS)          # needs the fused launch
+    assert ei.value.code == hl.HL_E_INVAL
 
 
 @pytest.mark.parametrize("order,sched", [(1, 0), (2, 0), (3, 0), (4, 0), (6, 0), (8, 0), (8, 2), (8, 3), (2, 2), (0, 3),
