@@ -1187,6 +1187,7 @@ static int init_t(const KArgs &a0, int n_entries, int block, hipStream_t st) {
     KArgs a = a0;
     a.e_off = 0;
     a.xcd_remap = 0;
+    a.emap = nullptr;  // one work-group per entry, in entry order
     hipLaunchKernelGGL((k_step<T, M_RAW>), dim3(n_entries), dim3(block), 0, st, a);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_RAW);
     return (int)hipGetLastError();
