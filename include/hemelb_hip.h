@@ -337,6 +337,24 @@ int hl_read_density_device(hl_ctx *ctx, int32_t dom, void *dptr);
 int hl_read_velocity_device(hl_ctx *ctx, int32_t dom, void *dptr);
 int hl_read_wss_device(hl_ctx *ctx, int32_t dom, void *dptr);
 
+/* Allocation-free variant of the three device reads above, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Writes the domain's density (double [n]),
+ * velocity (double [3][n]) and wall shear stress (double [n]) at step t, in
+ * caller order, into the caller's device buffers rho, u and wss (any of them
+ * may be NULL to skip it), on the context stream, with the same values as
+ * hl_read_density_device, hl_read_velocity_device and hl_read_wss_device.
+ * It calls no hipMalloc, hipFree or allocating routine: the observables are
+ * staged through a fixed device scratch array of the library (64 MiB on every
+ * device the library runs on, held until the process ends), in passes of
+ * 1,677,696 internal sites, so contexts of any size are served.  Every call on
+ * one device shares that scratch: calls that overlap on one device (other
+ * streams, other threads, other contexts) race and must be serialised by the
+ * caller.  The context must be committed (hl_commit, or a step or read before)
+ * because committing allocates.  Errors: HL_E_RANGE (domain), HL_E_STATE (not
+ * committed), HL_E_DEVICE (a launch failed). */
+int hl_read_observables_device_noalloc(hl_ctx *ctx, int32_t dom, void *rho, void *u, void *wss);
+
 /* ---- checkpoints ------------------------------------------------------------ */
 
 /* Copy the complete dynamic state (both population lattices, outlet velocity

@@ -275,6 +275,15 @@ class Context:
     def wss_device(self, dom, dst):
         return self._device(self._l.hl_read_wss_device, "hl_read_wss_device", dom, dst)
 
+    def observables_device_noalloc(self, dom, rho=None, u=None, wss=None):
+        """Density, velocity and wall shear stress into caller device buffers
+        (torch tensors or raw pointers; None skips one) without any device
+        allocation (``hl_read_observables_device_noalloc``)."""
+        ptr = [ct.c_void_p(0 if b is None else (b.data_ptr() if hasattr(b, "data_ptr") else int(b)))
+               for b in (rho, u, wss)]
+        return self._chk(self._l.hl_read_observables_device_noalloc(self._h, dom, *ptr),
+                         "hl_read_observables_device_noalloc")
+
     # -- checkpoints, schedule -------------------------------------------
     def get_state(self):
         n = ct.c_size_t(0)

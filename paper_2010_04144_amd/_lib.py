@@ -112,6 +112,7 @@ SIGNATURES = {
     "hl_read_density_device": (_I, [_P, _I32, _P]),
     "hl_read_velocity_device": (_I, [_P, _I32, _P]),
     "hl_read_wss_device": (_I, [_P, _I32, _P]),
+    "hl_read_observables_device_noalloc": (_I, [_P, _I32, _P, _P, _P]),
     "hl_get_state": (_I, [_P, _P, ct.POINTER(ct.c_size_t)]),
     "hl_set_state": (_I, [_P, _P, ct.c_size_t]),
     "hl_autotune": (_I, [_P, _I]),

@@ -192,6 +192,9 @@ hl::KArgs make_args(hl_ctx *c) {
     a.bc = c->d_bc;
     a.held = c->d_held;
     a.obs = c->d_obs;
+    a.obs_lo = 0;
+    a.obs_hi = c->L.N;
+    a.obs_stride = c->L.N;
     a.fout = nullptr;
     a.fin = nullptr;
     return a;
@@ -419,6 +422,14 @@ int commit(hl_ctx *c) {
         HIPC(c, hipMemcpy(c->d_pairs, c->L.hpairs.data(), c->L.hpairs.size() * sizeof(hl::PairDev),
                           hipMemcpyHostToDevice));
     if ((rc = upload_schedule(c)) != HL_OK) return rc;
+    // caller index -> internal index per domain, for the device reads
+    c->d_c2g.assign(c->doms.size(), nullptr);
+    for (int d = 0; d < D; ++d) {
+        if ((rc = dalloc(c, &c->d_c2g[d], c->doms[d].n)) != HL_OK) return rc;
+        if (c->doms[d].n)
+            HIPC(c, hipMemcpy(c->d_c2g[d], c->doms[d].c2g.data(), c->doms[d].n * sizeof(int64_t),
+                              hipMemcpyHostToDevice));
+    }
     std::vector<double> held(nio1, 0.0), zeros(2 * nio1, 0.0);
     for (int d = 0; d < D; ++d)
         for (int k = 0; k < c->doms[d].n_iolet; ++k) held[c->doms[d].io_base + k] = c->doms[d].io[k].wave.at(0.0);
@@ -522,6 +533,9 @@ int hl_create(hl_ctx **out, int device, int precision, uint64_t flags) {
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HL_E_DEVICE;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HL_E_DEVICE;
     if (hipSetDevice(device) != hipSuccess) return HL_E_DEVICE;
+    // once per device: the address of the fixed scratch of the
+    // allocation-free observables read
+    if (hl::noalloc_scratch_setup(device) != (int)hipSuccess) return HL_E_DEVICE;
     hl_ctx *c = new hl_ctx();
     c->device = device;
     c->precision = precision;
@@ -871,15 +885,46 @@ static int read_device(hl_ctx *ctx, int32_t dom, int comp, int ncomp, void *dptr
     HIPC(ctx, hipSetDevice(ctx->device));
     if ((rc = observe(ctx, false)) != HL_OK) return rc;
     Domain &d = ctx->doms[dom];
-    if (ctx->d_c2g.size() != ctx->doms.size()) ctx->d_c2g.assign(ctx->doms.size(), nullptr);
-    if (!ctx->d_c2g[dom]) {
-        if ((rc = dalloc(ctx, &ctx->d_c2g[dom], d.n)) != HL_OK) return rc;
-        HIPC(ctx, hipMemcpy(ctx->d_c2g[dom], d.c2g.data(), d.n * sizeof(int64_t), hipMemcpyHostToDevice));
-    }
     for (int m = 0; m < ncomp; ++m) {
         int e = hl::launch_gather_obs(ctx->d_obs + (size_t)(comp + m) * ctx->L.N, ctx->d_c2g[dom], d.n,
-                                      (double *)dptr + (size_t)m * d.n, ctx->stream);
+                                      (double *)dptr + (size_t)m * d.n, 0, ctx->L.N, ctx->stream);
         if (e != 0) return fail(ctx, HL_E_DEVICE, "gather launch failed");
+    }
+    return HL_OK;
+}
+
+int hl_read_observables_device_noalloc(hl_ctx *ctx, int32_t dom, void *rho, void *u, void *wss) {
+    int rc = check_dom(ctx, dom);
+    if (rc) return rc;
+    if (!ctx->committed) return fail(ctx, HL_E_STATE, "the context must be committed first (this call allocates nothing)");
+    if (!rho && !u && !wss) return HL_OK;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    double *scr = hl::noalloc_scratch(ctx->device);
+    if (!scr) return fail(ctx, HL_E_DEVICE, "no scratch address for device %d", ctx->device);
+    // passes over windows of W internal sites: the observables of a window
+    // are staged in the scratch ([5][W] doubles) and scattered to the caller
+    // order; the next pass reuses the scratch (same stream)
+    const int64_t W = hl::NOALLOC_SCRATCH_DOUBLES / 5 / hl::TILE * hl::TILE;
+    const Domain &d = ctx->doms[dom];
+    void *outs[3] = {rho, u, wss};
+    const int comps[3] = {0, 1, 4}, ncomp[3] = {1, 3, 1};
+    for (int64_t g0 = 0; g0 < ctx->L.N; g0 += W) {
+        hl::KArgs a = make_args(ctx);
+        a.obs = scr;
+        a.obs_lo = g0;
+        a.obs_hi = std::min(g0 + W, ctx->L.N);
+        a.obs_stride = W;
+        a.fout = nullptr;
+        int e = hl::launch_observe(ctx->precision, a, (int)ctx->L.entries.size(), ctx->block, ctx->stream);
+        if (e != 0) return fail(ctx, HL_E_DEVICE, "observe launch failed: %s", hipGetErrorString((hipError_t)e));
+        for (int q = 0; q < 3; ++q) {
+            if (!outs[q]) continue;
+            for (int m = 0; m < ncomp[q]; ++m) {
+                e = hl::launch_gather_obs(scr + (size_t)(comps[q] + m) * W, ctx->d_c2g[dom], d.n,
+                                          (double *)outs[q] + (size_t)m * d.n, a.obs_lo, a.obs_hi, ctx->stream);
+                if (e != 0) return fail(ctx, HL_E_DEVICE, "gather launch failed");
+            }
+        }
     }
     return HL_OK;
 }

@@ -111,7 +111,8 @@ struct KArgs {
     double *stats;     // [2][n_io]: mean u.n, mean rho
     double *bc;        // [2][n_io] boundary values by step parity
     double *held;      // [n_io] held coupled values
-    double *obs;       // [5][N] rho, ux, uy, uz, wss
+    double *obs;       // [5][obs_stride] rho, ux, uy, uz, wss of the sites in [obs_lo, obs_hi)
+    int64_t obs_lo, obs_hi, obs_stride;
     double *fout;      // [19][N] full f(t) or null
     const double *fin; // [19][N] full f(t) to load
 };
@@ -127,7 +128,18 @@ int launch_init(int prec, const KArgs &a, int n_entries, int block, void *stream
 int launch_observe(int prec, const KArgs &a, int n_entries, int block, void *stream);
 int launch_load_raw(int prec, const KArgs &a, void *stream);
 int launch_fill_rest(int prec, const KArgs &a, void *stream);
-int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *out, void *stream);
+// out[k] = src[c2g[k] - lo] for the caller sites k < n whose internal index
+// lies in [lo, hi) (the others are left as they are).
+int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *out, int64_t lo, int64_t hi,
+                      void *stream);
+// Fixed device scratch of the allocation-free observables read: a file-scope
+// device array of NOALLOC_SCRATCH_DOUBLES doubles in each device's copy of the
+// library.  noalloc_scratch_setup() looks up its device address once per
+// device (call it with that device current; returns a hipError_t value);
+// noalloc_scratch() returns the address found for a device, or null.
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = (int64_t)8 << 20;  // 64 MiB
+int noalloc_scratch_setup(int device);
+double *noalloc_scratch(int device);
 // In-place (AA-pattern) scheme: one sweep t -> t+1 (odd = t & 1), and the
 // moments-only pass that computes the iolet means and boundary values of t.
 int launch_aa_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part, bool fused,

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "hl_internal.h"
@@ -1022,6 +1023,7 @@ __global__ void __launch_bounds__(256) k_observe(KArgs a) {
     const SegDev &sg = a.seg[e.seg];
     if ((int)threadIdx.x >= e.count) return;
     const int64_t s = (int64_t)e.start + threadIdx.x;
+    if (s < a.obs_lo || s >= a.obs_hi) return;  // outside this pass's window
     const int64_t N = a.N;
     R x[Q];
     if (a.aa) {
@@ -1081,11 +1083,12 @@ __global__ void __launch_bounds__(256) k_observe(KArgs a) {
             wss = sqrt(sx * sx + sy * sy + sz * sz);
         }
     }
-    a.obs[s] = rho;
-    a.obs[N + s] = ux;
-    a.obs[2 * N + s] = uy;
-    a.obs[3 * N + s] = uz;
-    a.obs[4 * N + s] = wss;
+    const int64_t w = s - a.obs_lo, W = a.obs_stride;
+    a.obs[w] = rho;
+    a.obs[W + w] = ux;
+    a.obs[2 * W + w] = uy;
+    a.obs[3 * W + w] = uz;
+    a.obs[4 * W + w] = wss;
     if (a.fout) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) a.fout[(size_t)i * N + s] = f[i];
@@ -1127,9 +1130,39 @@ __global__ void k_fill_rest(KArgs a) {
 
 // obs component (internal order) -> caller order, in device memory.
 __global__ void k_gather_obs(const double *__restrict__ src, const int64_t *__restrict__ c2g, int64_t n,
-                             double *__restrict__ out) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-        out[k] = src[c2g[k]];
+                             double *__restrict__ out, int64_t lo, int64_t hi) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = c2g[k];
+        if (g >= lo && g < hi) out[k] = src[g - lo];
+    }
+}
+
+// Staging of the allocation-free observables read (see hl_internal.h).  In
+// host code `scratch` names a host-side stand-in, never the device array:
+// kernels receive the address hipGetSymbolAddress returns for the device.
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+int noalloc_scratch_setup(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return (int)hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    g_scratch_ptr[device] = (double *)ptr;
+    return (int)hipSuccess;
+}
+
+double *noalloc_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 // Full f(t) (double, internal order) -> the in-place lattice at an odd step,
@@ -1295,9 +1328,10 @@ int launch_aa_load_odd(int prec, const KArgs &a, int n_entries, int block, void 
     });
 }
 
-int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *out, void *stream) {
+int launch_gather_obs(const double *src, const int64_t *c2g, int64_t n, double *out, int64_t lo, int64_t hi,
+                      void *stream) {
     if (n <= 0) return 0;
-    hipLaunchKernelGGL(k_gather_obs, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, src, c2g, n, out);
+    hipLaunchKernelGGL(k_gather_obs, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, src, c2g, n, out, lo, hi);
     return (int)hipGetLastError();
 }
 
