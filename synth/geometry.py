@@ -350,3 +350,48 @@ def tubes(count=1, radius=4.0, length=24, gap=3, q="half", seed=0):
     if q == "random":
         g = g.with_q("random", seed=seed)
     return g
+
+
+def long_pipe(nx, ny, radius, nz, q="half"):
+    """z-periodic straight pipe of nz slices, fluid iff (x-ax)^2 + (y-ay)^2 <
+    R^2, built without a dense grid: the neighbour table of the middle slice
+    of a 3-slice periodic cylinder is repeated along z (sites numbered slice by
+    slice, the same in-slice order as ``cylinder``).  ``q``: ``half`` or
+    ``cylinder`` (exact ray / circle wall fractions, the same in every slice).
+    For site lists whose element count 19 n exceeds 2^31."""
+    base = cylinder(nx=nx, ny=ny, nz=3, radius=radius, ends="periodic", q=q)
+    S = base.meta["sites_per_slice"]
+    n = S * nz
+    if n >= 2**31 - 1:
+        raise ValueError("site count exceeds the int32 index range")
+    mid = base.nbr[:, S:2 * S].astype(np.int64)
+    nbr = np.empty((NDIR, n), np.int32)
+    z = np.arange(nz, dtype=np.int64)
+    for i in range(NDIR):
+        cz = int(DIRS[i, 2])
+        row = mid[i]
+        wall = row < 0
+        kp = np.where(wall, 0, row - (1 + cz) * S)        # in-slice index of the neighbour
+        zz = (z + cz) % nz
+        out = nbr[i].reshape(nz, S)
+        for z0 in range(0, nz, 4096):
+            z1 = min(nz, z0 + 4096)
+            blk = zz[z0:z1, None] * S + kp[None, :]
+            blk[:, wall] = -1
+            out[z0:z1] = blk
+    coords = np.empty((3, n), np.int32)
+    coords[0] = np.tile(base.coords[0, :S], nz)
+    coords[1] = np.tile(base.coords[1, :S], nz)
+    coords[2] = np.repeat(np.arange(nz, dtype=np.int32), S)
+    g = Geometry(coords, nbr, [], (nx, ny, nz),
+                 meta=dict(kind="long pipe", radius=radius, axis=base.meta["axis"], ends="periodic",
+                           sites_per_slice=int(S), slices=int(nz)))
+    if q != "half":
+        sel = (base.q_site >= S) & (base.q_site < 2 * S)
+        ks, kd, kq = base.q_site[sel] - S, base.q_dir[sel], base.q[sel]
+        m = ks.size
+        g.q_site = (np.arange(nz, dtype=np.int64)[:, None] * S + ks[None, :]).ravel()
+        g.q_dir = np.tile(kd, nz)
+        g.q = np.tile(kq, nz)
+        assert g.q_site.size == m * nz
+    return g

@@ -78,8 +78,47 @@ def pulsatile(rng, mean=0.01, spread=0.003, harmonics=3, period=None):
     return (mean, tuple(a), tuple(b), T)
 
 
+def _tree_job(job):
+    depth, r0, seed, kw = job
+    return tree_geometry(depth, r0, seed, **kw)
+
+
+def build_trees(jobs, workers=1, progress=None):
+    """tree_geometry(depth, r0, seed, **kw) for every (depth, r0, seed, kw) in
+    jobs, in that order; with workers > 1 in forked worker processes (largest
+    trees first), which must happen before the calling process touches a
+    GPU.  The result does not depend on the number of workers."""
+    if workers <= 1 or len(jobs) <= 1:
+        out = []
+        for j in jobs:
+            out.append(_tree_job(j))
+            if progress is not None:
+                progress(f"tree {len(out)}/{len(jobs)}: {out[-1].n} sites")
+        return out
+    import multiprocessing as mp
+    order = sorted(range(len(jobs)), key=lambda k: -(jobs[k][1] ** 3) * jobs[k][3].get("radius_scale", 1.0) ** 2)
+    out = [None] * len(jobs)
+    with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+        for k, geo in zip(order, pool.imap(_tree_job, [jobs[k] for k in order], chunksize=1)):
+            out[k] = geo
+            if progress is not None:
+                progress(f"tree {sum(g is not None for g in out)}/{len(jobs)}: {geo.n} sites")
+    return out
+
+
+def coupled_lambda(depth=6, r0=48.0, seed=MASTER_SEED + 4, arterial_sites=60e6):
+    """Segment length / radius ratio for which the arterial tree of the
+    coupled pair holds about `arterial_sites` sites.  The segments' volume
+    grows linearly with it and the joints' does not, so two probe trees of the
+    same shape at half the radius (1/8 of the volume) fix a line n(lambda)."""
+    n8 = tree_geometry(depth, r0 / 2.0, seed, lam=8.0).n * 8.0
+    n16 = tree_geometry(depth, r0 / 2.0, seed, lam=16.0).n * 8.0
+    slope = (n16 - n8) / 8.0
+    return float(8.0 + (arterial_sites - n8) / slope)
+
+
 def coupled_pair(depth=6, r0=48.0, lam=None, vein_scale=1.5, seed=MASTER_SEED + 4, period=4000.0,
-                 tau=0.8, steps=20000, progress=None):
+                 tau=0.8, steps=20000, progress=None, workers=1):
     """Arterial tree (root velocity inlet, leaf pressure outlets) coupled 1:1
     at every leaf to the mirrored venous tree of the same seeded topology with
     radii scaled by vein_scale (leaf velocity inlets, root pressure outlet).
@@ -88,12 +127,11 @@ def coupled_pair(depth=6, r0=48.0, lam=None, vein_scale=1.5, seed=MASTER_SEED + 
     rng = np.random.default_rng(seed)
     if lam is None:
         lam = 8.0
-    art = tree_geometry(depth, r0, seed, lam=lam)
+    art, ven = build_trees([(depth, r0, seed, dict(lam=lam)),
+                            (depth, r0, seed, dict(lam=lam, radius_scale=vein_scale, mirror=True, venous=True))],
+                           workers=workers)
     if progress is not None:
-        progress(f"arterial tree: {art.n} sites")
-    ven = tree_geometry(depth, r0, seed, lam=lam, radius_scale=vein_scale, mirror=True, venous=True)
-    if progress is not None:
-        progress(f"venous tree: {ven.n} sites")
+        progress(f"arterial tree: {art.n} sites; venous tree: {ven.n} sites")
     inlet = pulsatile(rng, period=period)
     a = DomainSpec(art, tau, bouzidi=True, inlets={0: inlet})
     v = DomainSpec(ven, tau, bouzidi=True, outlets={0: (1.0, (), (), 1.0)})
@@ -118,19 +156,19 @@ def _iolet_areas(geo):
     return out
 
 
-def ensemble(count=32, lo=5e5, hi=8e6, depth=6, lam=8.0, seed=MASTER_SEED + 5, steps=2000, progress=None):
+def ensemble(count=32, lo=5e5, hi=8e6, depth=6, lam=8.0, seed=MASTER_SEED + 5, steps=2000, progress=None,
+             workers=1):
     """count trees with site counts log-uniform in [lo, hi] (root radius scaled
     to hit each target), each with its own tau in [0.52, 0.9] and a seeded
     3-harmonic inlet waveform with period in [1000, 4000].  progress(msg) is
     called after each tree."""
     rng = np.random.default_rng(seed)
     targets = np.exp(rng.uniform(np.log(lo), np.log(hi), size=count))
+    jobs = [(depth, float((nt / ((depth + 1) * np.pi * lam)) ** (1.0 / 3.0)), seed + 100 + m, dict(lam=lam))
+            for m, nt in enumerate(targets)]
+    geos = build_trees(jobs, workers=workers, progress=progress)
     doms = []
-    for m, nt in enumerate(targets):
-        r0 = float((nt / ((depth + 1) * np.pi * lam)) ** (1.0 / 3.0))
-        geo = tree_geometry(depth, r0, seed + 100 + m, lam=lam)
-        if progress is not None:
-            progress(f"tree {m + 1}/{count}: {geo.n} sites")
+    for m, geo in enumerate(geos):
         tau = float(rng.uniform(0.52, 0.9))
         inlet = pulsatile(rng)
         outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}

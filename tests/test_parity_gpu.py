@@ -110,16 +110,39 @@ def test_coupled_1to3_fp64(hl, oracle_mod, mode):
         np.testing.assert_allclose(g.iolet_bc(d, which=1), o.last_bc(d), rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("prec,bound_u,bound_rho", [("f32", 2e-4, 2e-4), ("f16", 0.05, 0.05), ("f16w", 0.05, 0.05),
-                                                    ("f16sr", 0.05, 0.05)])
-def test_offset_storage_errors(hl, oracle_mod, prec, bound_u, bound_rho):
+# Errors of the reduced-precision storage forms against the FP64 oracle on the
+# cylinder after 1000 steps (two lattices and in place), measured on the
+# MI355X; each bound is about four times the larger of the two measurements,
+# so a regression of the stored precision or of the FP32 arithmetic shows.
+#        measured (two lattices / in place)
+# f32    e_u 2.36e-6/2.31e-6  e_rho 1.52e-6/1.56e-6  e_f 1.71e-6/1.78e-6  e_wss 1.33e-6/1.34e-6
+#        e_iolet_u 1.62e-6/1.59e-6  e_iolet_p 2.16e-6/2.10e-6
+# f16    e_u 7.49e-4  e_rho 4.99e-4  e_f 6.84e-4  e_wss 7.70e-4  e_iolet_u 1.77e-4  e_iolet_p 9.83e-5 (both)
+# f16w   e_u 8.23e-4  e_rho 1.02e-3  e_f 1.28e-3  e_wss 1.34e-3  e_iolet_u 3.65e-4  e_iolet_p 6.43e-4 (both)
+# f16sr  e_u 3.62e-4/4.06e-4  e_rho 4.58e-4/4.94e-4  e_f 7.87e-4/9.66e-4  e_wss 1.22e-3/1.08e-3
+#        e_iolet_u 1.66e-5/6.86e-5  e_iolet_p 3.27e-5/8.42e-6
+OFFSET_BOUNDS = {
+    "f32": dict(e_u=1e-5, e_rho=7e-6, e_f=8e-6, e_wss=6e-6, e_iolet_u=7e-6, e_iolet_p=9e-6),
+    "f16": dict(e_u=3e-3, e_rho=2e-3, e_f=3e-3, e_wss=3e-3, e_iolet_u=8e-4, e_iolet_p=4e-4),
+    "f16w": dict(e_u=3.5e-3, e_rho=4e-3, e_f=5e-3, e_wss=5.5e-3, e_iolet_u=1.5e-3, e_iolet_p=2.6e-3),
+    "f16sr": dict(e_u=1.7e-3, e_rho=2e-3, e_f=4e-3, e_wss=5e-3, e_iolet_u=3e-4, e_iolet_p=1.4e-4),
+}
+
+
+def check_bounds(prec, err):
+    bad = {k: (v, OFFSET_BOUNDS[prec][k]) for k, v in err.items() if not v <= OFFSET_BOUNDS[prec][k]}
+    assert not bad, (prec, bad, err)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "f16w", "f16sr"])
+def test_offset_storage_errors(hl, oracle_mod, prec):
     """FP32 / FP16 storage of f - w rho0 with FP32 arithmetic on the cylinder
-    after 1000 steps: the errors against the FP64 oracle are reported and
-    bounded."""
+    after 1000 steps: every error against the FP64 oracle (velocity, density,
+    populations, wall shear stress, iolet means) is reported and bounded."""
     g, o = run_both(cylinder_scenario(), hl, oracle_mod, 1000, precision=prec)
     err = errors(g, o, with_f=True, with_wss=True)
     print(prec, "cylinder errors vs oracle", err, flush=True)
-    assert err["e_u"] < bound_u and err["e_rho"] < bound_rho
+    check_bounds(prec, err)
 
 
 def test_rest_state_stays_exact(hl):
@@ -513,15 +536,16 @@ def test_aa_checkpoint_graph_and_reload(hl, prec):
 
 
 def test_aa_offset_storage_errors(hl, oracle_mod):
-    for prec, bound in (("f32", 2e-4), ("f16", 0.05), ("f16w", 0.05), ("f16sr", 0.05)):
-        sc = cylinder_scenario()
-        o = build_oracle(sc, oracle_mod)
+    sc = cylinder_scenario()
+    o = build_oracle(sc, oracle_mod)
+    o.step(1000)
+    for prec in ("f32", "f16", "f16w", "f16sr"):
         g = build_gpu(sc, hl, prec, order=AA)
-        o.step(1000)
         g.step(1000)
         err = errors(g, o)
+        g.close()
         print("AA", prec, err, flush=True)
-        assert err["e_u"] < bound
+        check_bounds(prec, err)
 
 
 @pytest.mark.parametrize("order", [0, AA | 8])
@@ -537,14 +561,19 @@ def test_scaled_fp16_slow_flow(hl, oracle_mod, order):
     o = build_oracle(sc, oracle_mod)
     o.step(1500)
     res = {}
+    # measured: f16 e_u 1.03e-3 e_rho 2.17e-4 e_wss 2.14e-3; f16w 8.41e-4, 1.97e-4, 1.32e-3;
+    # f16sr 4.41e-4 / 4.19e-4 (order 0 / in place), 8.13e-5, 2.23e-3 (bounds about 4x)
+    bounds = {"f16": dict(e_u=4e-3, e_rho=9e-4, e_wss=9e-3), "f16w": dict(e_u=3.5e-3, e_rho=8e-4, e_wss=5.5e-3),
+              "f16sr": dict(e_u=1.8e-3, e_rho=3.3e-4, e_wss=9e-3)}
     for prec in ("f16", "f16w", "f16sr"):
         g = build_gpu(sc, hl, prec, order=order)
         g.step(1500)
         res[prec] = errors(g, o, with_wss=True)
         print("slow cylinder", prec, "order", order, res[prec], flush=True)
         g.close()
+        bad = {k: v for k, v in bounds[prec].items() if not res[prec][k] <= v}
+        assert not bad, (prec, bad, res[prec])
     assert res["f16w"]["e_u"] <= res["f16"]["e_u"]
-    assert res["f16w"]["e_u"] < 0.05
 
 
 @pytest.mark.parametrize("order", [0, AA | 8])

@@ -40,21 +40,117 @@ def test_branching_artery_full_size(hl, oracle_mod):
     o.step(5, min(16, os.cpu_count() or 1))
     sched = hl.HL_SCHED_FUSED | hl.HL_SCHED_XCD_REMAP | hl.HL_SCHED_XCD_RUNS
     bricks = hl.HL_ORDER_BRICK | hl.HL_ORDER_BRICK_32
-    for prec, order, bound in (("f64", bricks, TOL64), ("f32", bricks, 1e-3),
-                               ("f16", bricks | hl.HL_SCHEME_AA, 2e-2)):
+    # reduced precision, measured: f32 e_u 3.2e-7 e_rho 3.3e-7 e_f 5.6e-7 e_wss 3.1e-7 e_iolet_u 5.2e-8
+    # e_iolet_p 3.1e-8; f16 e_u 2.3e-4 e_rho 2.9e-4 e_f 5.9e-4 e_wss 6.0e-4 e_iolet_u 9.6e-7 e_iolet_p 1.3e-7
+    # (bounds about 4x)
+    bounds = {"f64": {k: TOL64 for k in ("e_u", "e_rho", "e_f", "e_wss", "e_iolet_u", "e_iolet_p")},
+              "f32": dict(e_u=1.3e-6, e_rho=1.3e-6, e_f=2.3e-6, e_wss=1.3e-6, e_iolet_u=2.1e-7, e_iolet_p=1.3e-7),
+              "f16": dict(e_u=1e-3, e_rho=1.2e-3, e_f=2.4e-3, e_wss=2.4e-3, e_iolet_u=4e-6, e_iolet_p=5.2e-7)}
+    for prec, order in (("f64", bricks), ("f32", bricks), ("f16", bricks | hl.HL_SCHEME_AA)):
         print(f"branching artery full size: {prec} layout {order}", flush=True)
         g = build_gpu(sc, hl, prec, order=order)
         g.commit()
         g.set_schedule(256, sched)
         g.step(5)
-        full = prec == "f64"
-        err = errors(g, o, 0, with_f=full, with_wss=full)
+        err = errors(g, o, 0)
         g.close()
         print(f"branching artery full size {prec}: {err}", flush=True)
-        if full:
-            assert max(err.values()) <= bound, err
-        else:
-            assert err["e_u"] < bound and err["e_iolet_u"] < bound, err
+        bad = {k: v for k, v in err.items() if not v <= bounds[prec][k]}
+        assert not bad, (prec, bad, err)
+
+
+# errors after three steps from the developed FP64 state, measured on the
+# MI355X: f32 e_u 6.0e-7 e_rho 4.1e-7 e_f 1.09e-6 e_wss 5.0e-7 e_iolet_u 6.2e-8
+# e_iolet_p 8.0e-7; f16 (in place) 3.8e-4, 5.6e-4, 1.48e-3, 7.0e-4, 9.3e-6, 6.6e-6
+# (the bounds are about four times these)
+DEVELOPED_BOUNDS = {"f32": dict(e_u=2.5e-6, e_rho=1.7e-6, e_f=4.4e-6, e_wss=2e-6, e_iolet_u=2.5e-7, e_iolet_p=3.2e-6),
+                    "f16": dict(e_u=1.5e-3, e_rho=2.2e-3, e_f=6e-3, e_wss=2.8e-3, e_iolet_u=3.7e-5, e_iolet_p=2.6e-5)}
+
+
+def test_branching_artery_developed_flow(hl, oracle_mod):
+    """The benchmark workload at full size with developed flow: 2000 FP64
+    steps (the acoustic front has crossed the tree three times, so every
+    outlet and Bouzidi wall carries non-rest values); the GPU's populations
+    are then loaded into the oracle and both advance three more steps, after
+    which every output must agree to 1e-12.  The FP32 (two lattices) and FP16
+    (in place) forms, loaded with the same developed state, report their
+    three-step errors against the same oracle result."""
+    geo = synth.branching_artery(box=768)
+    sc = Scenario([Dom(geo, tau=0.55, bouzidi=True, inlets={0: (0.01, (), (), 1.0)})])
+    sched = hl.HL_SCHED_FUSED | hl.HL_SCHED_XCD_REMAP | hl.HL_SCHED_XCD_RUNS
+    bricks = hl.HL_ORDER_BRICK | hl.HL_ORDER_BRICK_32
+    g = build_gpu(sc, hl, "f64", order=bricks)
+    g.commit()
+    g.set_schedule(256, sched)
+    g.step(2000)
+    f_dev = g.populations(0)
+    mu, _ = g.iolet_stats(0)
+    print("developed flow: inlet mean u", mu[0], "outlet mean u min/max", np.abs(mu[1:]).min(),
+          np.abs(mu[1:]).max(), flush=True)
+    assert np.abs(mu[1:]).min() > 1e-6
+    o = build_oracle(sc, oracle_mod)
+    o.set_f(0, f_dev)
+    o.step(3, min(16, os.cpu_count() or 1))
+    g.step(3)
+    err = errors(g, o, 0)
+    g.close()
+    print("branching artery developed f64:", err, flush=True)
+    assert max(err.values()) <= TOL64, err
+    for prec, order in (("f32", bricks), ("f16", bricks | hl.HL_SCHEME_AA)):
+        g = build_gpu(sc, hl, prec, order=order)
+        g.commit()
+        g.set_schedule(256, sched)
+        g.set_populations(0, f_dev)
+        g.step(3)
+        err = errors(g, o, 0)
+        g.close()
+        print(f"branching artery developed {prec}:", err, flush=True)
+        bad = {k: v for k, v in err.items() if not v <= DEVELOPED_BOUNDS[prec][k]}
+        assert not bad, (prec, bad, err)
+
+
+def test_beyond_2_31_lattice_elements(hl, oracle_mod):
+    """A site list whose lattice has more than 2^31 elements (19 N > 2^31 once
+    N > 113 M: the element-count limit of Sec. 2.1, on the device): a
+    z-periodic pipe of radius 32 and 37,000 slices (119 M sites) with exact
+    ray/circle Bouzidi walls, driven by a uniform axial force.  The flow is
+    the same in every slice, so after 101 steps every slice of the GPU run must
+    equal the oracle's 4-slice pipe of the same cross-section to 1e-12, in the
+    two-lattice scheme (32^3 bricks, brick-aligned XCD runs) and in place.
+    (The force is large enough that the velocity, about 2e-3, is far above the
+    FP64 resolution of the populations: at 1e-4 after 51 steps the two
+    rounding orders already differ by 3e-12 of it.)"""
+    R, nxy, nz, steps = 32.0, 68, 37000, 101
+    F = (0.0, 0.0, 2e-5)
+    small = synth.cylinder(nx=nxy, ny=nxy, nz=4, radius=R, ends="periodic", q="cylinder")
+    S = small.meta["sites_per_slice"]
+    o = build_oracle(Scenario([Dom(small, tau=0.8, bouzidi=True, F0=F)]), oracle_mod)
+    o.step(steps, THREADS)
+    rho_r, u_r = o.moments(0)
+    rho_r, u_r = rho_r[:S], u_r[:, :S]
+    assert np.abs(rho_r - o.moments(0)[0][S:2 * S]).max() == 0.0        # the oracle's slices agree
+    geo = synth.long_pipe(nxy, nxy, R, nz, q="cylinder")
+    assert geo.n == S * nz and 19 * geo.n > 2 ** 31
+    sc = Scenario([Dom(geo, tau=0.8, bouzidi=True, F0=F)])
+    bricks = hl.HL_ORDER_BRICK | hl.HL_ORDER_BRICK_32
+    for order, sched in ((bricks, hl.HL_SCHED_FUSED | hl.HL_SCHED_XCD_BRICKS),
+                         (hl.HL_SCHEME_AA, hl.HL_SCHED_FUSED | hl.HL_SCHED_XCD_REMAP | hl.HL_SCHED_XCD_RUNS)):
+        print(f"long pipe {geo.n} sites (19 N = {19 * geo.n}), layout {order}", flush=True)
+        g = build_gpu(sc, hl, "f64", order=order)
+        g.set_schedule(256, sched)
+        g.commit()
+        info = g.info()
+        print(f"  committed: {info['device_bytes'] / 1e9:.1f} GB on the device", flush=True)
+        g.step(steps)
+        u = g.velocity(0).reshape(3, nz, S)
+        e_u = float(np.abs(u - u_r[:, None, :]).max() / np.abs(u_r).max())
+        del u
+        rho = g.density(0).reshape(nz, S)
+        e_rho = float(np.abs(rho - rho_r[None, :]).max() / max(np.abs(rho_r - 1.0).max(), 1e-2))
+        del rho
+        g.close()
+        print(f"  every slice vs the oracle's: e_u {e_u:.2e} e_rho {e_rho:.2e}", flush=True)
+        assert e_u <= TOL64 and e_rho <= TOL64, (order, e_u, e_rho)
 
 
 def womersley_error(ctx, wl, phases=8):
@@ -93,7 +189,9 @@ def test_womersley_full_size(hl, alpha):
               flush=True)
     assert res["f64"][0] < 0.03
     u64 = res["f64"][1]
-    for prec, bound in (("f32", 1e-4), ("f16", 2e-2), ("f16w", 2e-2), ("f16sr", 2e-2)):
+    # measured (alpha 10 / 4): f32 5.9e-6 / 1.8e-5; f16 5.4e-4 / 1.1e-3; f16w 1.7e-3 / 9.6e-4;
+    # f16sr 6.3e-4 / 6.8e-4 (bounds about 4x the larger)
+    for prec, bound in (("f32", 7e-5), ("f16", 4.5e-3), ("f16w", 7e-3), ("f16sr", 2.8e-3)):
         e_u = np.abs(res[prec][1] - u64).max() / np.abs(u64).max()
         print(f"womersley alpha={alpha} {prec} vs f64: e_u={e_u:.2e}", flush=True)
         assert e_u < bound
@@ -119,10 +217,14 @@ def test_coupled_pair_twin(hl, oracle_mod, order):
         np.testing.assert_allclose(g.iolet_bc(d, which=1), o.last_bc(d), rtol=1e-12, atol=1e-15)
     g32 = build_gpu(sc, hl, "f32", order=order)
     g32.step(800)
+    # measured (artery / vein): e_u 2.2e-6 / 8.9e-6, e_rho 5.3e-6 / 2.5e-6, e_iolet_u 2.2e-6 / 9.7e-6,
+    # e_iolet_p 4.7e-6 / 1.1e-5 (bounds about 4x the larger)
+    b32 = dict(e_u=3.6e-5, e_rho=2.2e-5, e_iolet_u=4e-5, e_iolet_p=4.6e-5)
     for d in (0, 1):
         err = errors(g32, o, d, with_f=False, with_wss=False)
         print("coupled twin fp32", d, err, flush=True)
-        assert err["e_u"] < 1e-3
+        bad = {k: v for k, v in err.items() if not v <= b32[k]}
+        assert not bad, (d, bad, err)
 
 
 def test_ensemble_twin(hl, oracle_mod):
