@@ -78,6 +78,14 @@ extern "C" {
 /* coupling modes */
 #define HL_ALTERNATE 0      /* forward on even steps, reverse on odd steps (Sec. 3) */
 #define HL_BOTH_EACH_STEP 1 /* both directions every step */
+/* bit, with either of the above: the reverse exchange drives each coupled
+ * arterial outlet as a velocity (Ladd) boundary, parabolic over its cut plane,
+ * whose site mean is the mean over its veins of mean_u(vein) / s_vel, instead
+ * of setting its pressure.  The second reading of the reverse direction of
+ * Sec. 3; it has no pressure feedback and grows without bound in the 1:3
+ * layout within about 100 steps, so it is offered for study, not as the
+ * default. */
+#define HL_COUPLE_VELOCITY 2
 
 /* step drivers */
 #define HL_DRIVE_LAUNCH 0 /* plain kernel launches per step */
@@ -122,9 +130,11 @@ extern "C" {
                                  bulk or the boundary path */
 #define HL_SCHED_XCD_RUNS 8u  /* with HL_SCHED_XCD_REMAP: runs of 64 consecutive site blocks go to the
                                  XCDs in turn instead of one contiguous range each */
-#define HL_SCHED_PAIRS 4u     /* bulk kernel with two adjacent sites per lane (vector loads/stores);
-                                 ignored with HL_SCHED_FUSED, HL_SCHEME_AA, HL_F16_SCALED and
-                                 HL_F16_STOCHASTIC */
+#define HL_SCHED_PAIRS 4u     /* two adjacent sites per lane on bulk sites (vector loads and stores where
+                                 the two sources are adjacent): the split schedule's bulk kernel, or,
+                                 with HL_SCHED_FUSED, the bulk work-groups of the fused launch (each then
+                                 takes up to twice the work-group size in sites); ignored with
+                                 HL_SCHEME_AA, HL_F16_SCALED and HL_F16_STOCHASTIC */
 #define HL_SCHED_XCD_BRICKS 16u /* with HL_SCHED_FUSED alone, in a brick layout: the work-groups are cut
                                  into runs of at least 64 that end only at brick boundaries, and each
                                  run goes to the XCD holding the fewest so far, so a brick's lines are
@@ -279,7 +289,8 @@ int hl_couple(hl_ctx *ctx, int32_t dom_a, int32_t outlet, int32_t dom_b, int32_t
               double dp_ratio);
 
 /* HL_ALTERNATE (default; Sec. 3: the direction alternates at each swap) or
- * HL_BOTH_EACH_STEP.  HL_E_STATE after the first step. */
+ * HL_BOTH_EACH_STEP, either optionally with HL_COUPLE_VELOCITY.  HL_E_INVAL
+ * for other bits; HL_E_STATE after the first step. */
 int hl_set_coupling_mode(hl_ctx *ctx, int mode);
 
 /* ---- stepping ---------------------------------------------------------------- */
@@ -371,7 +382,7 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes);
 /* Time candidate schedules for about budget_ms and keep the fastest: work-group
  * size {64, 128, 256} x {split, fused} x {plain, contiguous XCD ranges, XCD
  * runs}, the brick-aligned XCD runs in brick layouts, and the two-sites-per-
- * lane bulk kernel where it applies.  Every candidate is timed once; the three
+ * lane bulk path (split and fused) where it applies.  Every candidate is timed once; the three
  * fastest are then timed five more times each and the one with the lowest
  * median is kept.  The schedule, drive and dynamic state are restored on every
  * exit, including errors, so results do not change.  Infrastructure (the

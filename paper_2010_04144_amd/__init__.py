@@ -13,7 +13,7 @@ import ctypes as ct
 import numpy as np
 
 from . import _lib
-from ._lib import (HL_ALTERNATE, HL_BOTH_EACH_STEP, HL_DEBUG_CHECKS, HL_DRIVE_GRAPH, HL_DRIVE_LAUNCH,  # noqa: F401
+from ._lib import (HL_ALTERNATE, HL_BOTH_EACH_STEP, HL_COUPLE_VELOCITY, HL_DEBUG_CHECKS, HL_DRIVE_GRAPH, HL_DRIVE_LAUNCH,  # noqa: F401
                    HL_E_DEVICE, HL_E_DIVERGED, HL_E_INVAL, HL_E_NOMEM, HL_E_RANGE, HL_E_STATE,
                    HL_F16_OFFSET, HL_F16_SCALED, HL_F16_STOCHASTIC, HL_F32_OFFSET, HL_F64, HL_INLET_VEL, HL_OK,
                    HL_OUTLET_P, HL_ORDER_BOUNDARY_MORTON, HL_ORDER_BRICK, HL_ORDER_BRICK_32, HL_ORDER_BULK_MORTON,

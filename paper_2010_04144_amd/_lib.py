@@ -33,6 +33,7 @@ HL_INLET_VEL = 0
 HL_OUTLET_P = 1
 HL_ALTERNATE = 0
 HL_BOTH_EACH_STEP = 1
+HL_COUPLE_VELOCITY = 2
 HL_DRIVE_LAUNCH = 0
 HL_DRIVE_GRAPH = 1
 HL_SCHED_XCD_REMAP = 1

@@ -143,6 +143,11 @@ void free_device(hl_ctx *c) {
     c->dev_bytes = 0;
 }
 
+// Storage forms and schemes with the two-sites-per-lane bulk path.
+bool pairs_supported(const hl_ctx *c) {
+    return !c->aa && c->precision != hl::PREC_F16W && c->precision != hl::PREC_F16SR;
+}
+
 hl::KArgs make_args(hl_ctx *c) {
     hl::KArgs a{};
     a.N = c->L.N;
@@ -162,9 +167,9 @@ hl::KArgs make_args(hl_ctx *c) {
     a.bnrm = c->d_bnrm;
     a.entries = c->d_entries;
     a.entries2 = c->d_entries2;
-    a.n_pairs_blocks = ((c->sched_flags & HL_SCHED_PAIRS) && !(c->sched_flags & HL_SCHED_FUSED) && !c->aa &&
-                        c->precision != hl::PREC_F16W && c->precision != hl::PREC_F16SR)
+    a.n_pairs_blocks = ((c->sched_flags & HL_SCHED_PAIRS) && !(c->sched_flags & HL_SCHED_FUSED) && pairs_supported(c))
                            ? (int32_t)c->L.entries2.size() : 0;
+    a.pair_fused = (c->L.bulk_chunk > c->block) ? 1 : 0;
     a.seg = c->d_seg;
     a.io = c->d_io;
     a.pairs = c->d_pairs;
@@ -381,9 +386,9 @@ int ensure_stats(hl_ctx *c) {
 int commit(hl_ctx *c) {
     if (c->committed) return HL_OK;
     HIPC(c, hipSetDevice(c->device));
-    int rc = hl::plan_layout(c->doms, c->pairs, c->order_flags, c->L, c->err);
+    int rc = hl::plan_layout(c->doms, c->pairs, c->order_flags, c->couple_mode, c->L, c->err);
     if (rc != HL_OK) return rc;
-    hl::plan_schedule(c->L, c->block, c->sched_flags);
+    hl::plan_schedule(c->L, c->block, c->sched_flags, pairs_supported(c));
     if (c->debug_checks && (rc = hl::check_layout(c->doms, c->L, c->block, c->err)) != HL_OK) return rc;
     const int D = (int)c->doms.size();
     const int64_t Nio = c->L.Nio;
@@ -432,7 +437,12 @@ int commit(hl_ctx *c) {
     }
     std::vector<double> held(nio1, 0.0), zeros(2 * nio1, 0.0);
     for (int d = 0; d < D; ++d)
-        for (int k = 0; k < c->doms[d].n_iolet; ++k) held[c->doms[d].io_base + k] = c->doms[d].io[k].wave.at(0.0);
+        for (int k = 0; k < c->doms[d].n_iolet; ++k) {
+            // a velocity-driven coupled outlet starts from rest
+            const hl::IoletH &io = c->doms[d].io[k];
+            const bool vel_outlet = io.kind == hl::KIND_OUTLET && hl::velocity_driven(io, c->couple_mode);
+            held[c->doms[d].io_base + k] = vel_outlet ? 0.0 : io.wave.at(0.0);
+        }
     HIPC(c, hipMemcpy(c->d_held, held.data(), held.size() * 8, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_bc, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_stats, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice));
@@ -728,7 +738,7 @@ int hl_couple(hl_ctx *ctx, int32_t dom_a, int32_t outlet, int32_t dom_b, int32_t
 int hl_set_coupling_mode(hl_ctx *ctx, int mode) {
     if (!ctx) return HL_E_INVAL;
     if (ctx->committed) return fail(ctx, HL_E_STATE, "coupling mode cannot change after the first step");
-    if (mode != HL_ALTERNATE && mode != HL_BOTH_EACH_STEP) return fail(ctx, HL_E_INVAL, "unknown coupling mode");
+    if (mode & ~(HL_BOTH_EACH_STEP | HL_COUPLE_VELOCITY)) return fail(ctx, HL_E_INVAL, "unknown coupling mode");
     ctx->couple_mode = mode;
     return HL_OK;
 }
@@ -1039,14 +1049,14 @@ int hl_set_schedule(hl_ctx *ctx, int32_t block_size, int32_t flags) {
          !(ctx->order_flags & HL_ORDER_BRICK)))
         return fail(ctx, HL_E_INVAL, "HL_SCHED_XCD_BRICKS needs HL_SCHED_FUSED alone and a brick layout");
     const bool rebuild = block_size != ctx->block ||
-                         ((flags ^ ctx->sched_flags) & (HL_SCHED_FUSED | HL_SCHED_XCD_BRICKS));
+                         ((flags ^ ctx->sched_flags) & (HL_SCHED_FUSED | HL_SCHED_XCD_BRICKS | HL_SCHED_PAIRS));
     ctx->block = block_size;
     ctx->sched_flags = flags;
     if (!ctx->committed) return HL_OK;
     HIPC(ctx, hipSetDevice(ctx->device));
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     if (rebuild) {
-        hl::plan_schedule(ctx->L, ctx->block, ctx->sched_flags);
+        hl::plan_schedule(ctx->L, ctx->block, ctx->sched_flags, pairs_supported(ctx));
         return upload_schedule(ctx);
     }
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
@@ -1089,14 +1099,15 @@ int hl_autotune(hl_ctx *ctx, int budget_ms) {
     ctx->drive = HL_DRIVE_LAUNCH;
     struct Cand { int block, flags; double ms; };
     std::vector<Cand> cands;
-    const bool pairs_ok = !ctx->aa && ctx->precision != hl::PREC_F16W && ctx->precision != hl::PREC_F16SR;
+    const bool pairs_ok = pairs_supported(ctx);
     const bool bricks = (ctx->order_flags & HL_ORDER_BRICK) != 0;
     const int R1 = (int)HL_SCHED_XCD_REMAP, RR = (int)(HL_SCHED_XCD_REMAP | HL_SCHED_XCD_RUNS);
     const int F = (int)HL_SCHED_FUSED, P = (int)HL_SCHED_PAIRS, B = (int)HL_SCHED_XCD_BRICKS;
     for (int b : {64, 128, 256}) {
-        for (int f : {0, R1, RR, F, F | R1, F | RR, P, P | R1, P | RR})
+        for (int f : {0, R1, RR, F, F | R1, F | RR, P, P | R1, P | RR, F | P | RR})
             if (pairs_ok || !(f & HL_SCHED_PAIRS)) cands.push_back({b, f, 0.0});
         if (bricks) cands.push_back({b, F | B, 0.0});
+        if (bricks && pairs_ok) cands.push_back({b, F | P | B, 0.0});
     }
     HIPC(ctx, hipEventCreate(&guard.e0));
     HIPC(ctx, hipEventCreate(&guard.e1));

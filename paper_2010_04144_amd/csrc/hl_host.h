@@ -94,6 +94,7 @@ struct Layout {
     // brick-aligned XCD order (HL_SCHED_XCD_BRICKS): work-group b of the fused
     // launch takes entry emap[b], or nothing when emap[b] < 0
     std::vector<int32_t> emap;
+    int bulk_chunk = 0;  // sites per bulk entry (2 x block in the fused two-sites-per-lane schedule)
 };
 
 // Checks of a caller's site list (no device needed): codes in range, every
@@ -105,13 +106,20 @@ SegDev seg_of(const Domain &d);
 // Site order, pull tables, link data and iolet/pair tables of the domains.
 // Sets each domain's c2g and io_base.  Returns 0, or an HL_E_* code with a
 // message in err.
-int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint64_t order_flags, Layout &L,
-                std::string &err);
+// couple_mode: HL_COUPLE_VELOCITY makes every coupled outlet a velocity
+// (Ladd) boundary with the parabolic profile of its cut plane.
+int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint64_t order_flags, int couple_mode,
+                Layout &L, std::string &err);
+// True when iolet io takes the Ladd velocity rule.
+inline bool velocity_driven(const IoletH &io, int couple_mode) {
+    return io.kind == KIND_INLET || (io.coupled && (couple_mode & COUPLE_VEL));
+}
 
 // Work-group entries for `block` sites per work-group under the HL_SCHED_*
 // flags (and the brick-aligned XCD map when asked for), plus each iolet's
-// entry span.
-void plan_schedule(Layout &L, int block, int sched_flags);
+// entry span.  pair_bulk: with HL_SCHED_FUSED | HL_SCHED_PAIRS, bulk entries
+// hold up to 2 x block sites (the kernel takes two adjacent sites per lane).
+void plan_schedule(Layout &L, int block, int sched_flags, bool pair_bulk = false);
 
 // Exhaustive host check of a planned layout against the caller's site lists
 // (while they are still held): every internal index in range and on a real

@@ -40,7 +40,8 @@ constexpr int tag_class(int32_t tag) { return tag & ((1 << CLASS_BITS) - 1); }
 constexpr int tag_iolet(int32_t tag) { return tag >> CLASS_BITS; }
 enum : int32_t { KIND_INLET = 0, KIND_OUTLET = 1 };
 enum : int32_t { WALL_SBB = 0, WALL_BOUZIDI = 1 };
-enum : int32_t { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1 };
+// coupling mode bits: both directions every step; velocity-driven reverse
+enum : int32_t { COUPLE_ALTERNATE = 0, COUPLE_BOTH = 1, COUPLE_VEL = 2 };
 enum : int32_t { PREC_F64 = 0, PREC_F32 = 1, PREC_F16 = 2, PREC_F16W = 3, PREC_F16SR = 4 };
 
 // One work-group's share of sites: a contiguous internal range inside one
@@ -65,9 +66,9 @@ struct SegDev {
 struct IoletDev {
     double nrm[3];     // unit normal (into the fluid for inlets, out for outlets)
     double area;       // number of bordering sites
-    double phibar;     // mean inlet profile factor over those sites
+    double phibar;     // mean profile factor over those sites (velocity-driven iolets)
     double a0, a[MAXH], b[MAXH], period;
-    int32_t nh, kind, coupled, seg;
+    int32_t nh, kind, coupled, seg;  // kind: the link rule (KIND_INLET: Ladd velocity, KIND_OUTLET: pressure)
     int32_t e_lo, e_hi;       // schedule entries covering the iolet's sites
     int32_t pair_lo, pair_n;  // coupling pairs whose arterial outlet is this iolet
 };
@@ -103,6 +104,7 @@ struct KArgs {
     const Entry *entries2;   // bulk entries of 2 x block sites (two sites per lane)
     int32_t aa;              // 1: one in-place lattice (lat0), AA-pattern sweeps
     int32_t n_pairs_blocks;  // > 0: the bulk launch runs the two-sites-per-lane kernel
+    int32_t pair_fused;      // 1: fused launch whose bulk entries hold up to 2 x block sites, two per lane
     int32_t io_e0, io_e1;    // entry span covering every iolet's entries (empty: io_e0 == io_e1)
     const int32_t *emap;     // brick-aligned XCD order of the fused launch: work-group b takes entry
     int32_t n_emap;          // emap[b] (nothing when < 0); n_emap work-groups (null: storage order)

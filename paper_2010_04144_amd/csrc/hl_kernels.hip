@@ -107,8 +107,8 @@ __device__ __forceinline__ float ldc(const __half *p, int) { return __half2float
 __device__ __forceinline__ float ldc(const h16w *p, int row) { return __half2float(p->v) * wgt<float>(row); }
 __device__ __forceinline__ float ldc(const h16sr *p, int) { return __half2float(p->v); }
 // NT: non-temporal store (the two-lattice step writes a lattice it does not
-// read); the in-place sweeps store to lines they have just read and keep
-// them cached (NT = false).
+// read, in every storage form); the in-place sweeps store to lines they have
+// just read and keep them cached (NT = false).
 template <bool NT = true>
 __device__ __forceinline__ void stc(double *p, double v, int, uint32_t = 0) {
     if (NT)
@@ -123,14 +123,24 @@ __device__ __forceinline__ void stc(float *p, float v, int, uint32_t = 0) {
     else
         *p = v;
 }
-template <bool NT = true>
-__device__ __forceinline__ void stc(__half *p, float v, int, uint32_t = 0) { *p = __float2half_rn(v); }
-template <bool NT = true>
-__device__ __forceinline__ void stc(h16w *p, float v, int row, uint32_t = 0) {
-    p->v = __float2half_rn(v * (row == 0 ? 3.0f : (row <= 6 ? 18.0f : 36.0f)));
+// FP16 forms: the 16-bit pattern is stored as an unsigned short so that the
+// two-lattice step can store it non-temporally as well.
+template <bool NT>
+__device__ __forceinline__ void st16(void *p, __half h) {
+    const unsigned short bits = __half_as_ushort(h);
+    if (NT)
+        __builtin_nontemporal_store(bits, (unsigned short *)p);
+    else
+        *(unsigned short *)p = bits;
 }
 template <bool NT = true>
-__device__ __forceinline__ void stc(h16sr *p, float v, int, uint32_t key = 0) { p->v = half_sr(v, key); }
+__device__ __forceinline__ void stc(__half *p, float v, int, uint32_t = 0) { st16<NT>(p, __float2half_rn(v)); }
+template <bool NT = true>
+__device__ __forceinline__ void stc(h16w *p, float v, int row, uint32_t = 0) {
+    st16<NT>(p, __float2half_rn(v * (row == 0 ? 3.0f : (row <= 6 ? 18.0f : 36.0f))));
+}
+template <bool NT = true>
+__device__ __forceinline__ void stc(h16sr *p, float v, int, uint32_t key = 0) { st16<NT>(p, half_sr(v, key)); }
 
 // Lattice element of direction i at site s.  Sites are grouped in tiles of
 // TILE consecutive sites; a tile holds its 19 direction rows one after the
@@ -390,8 +400,8 @@ __global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
     }
     if (a.n_pairs > 0) {
         __syncthreads();
-        const bool fwd = a.couple_mode == COUPLE_BOTH || (tn % 2 == 0);
-        const bool rev = a.couple_mode == COUPLE_BOTH || (tn % 2 == 1);
+        const bool fwd = (a.couple_mode & COUPLE_BOTH) || (tn % 2 == 0);
+        const bool rev = (a.couple_mode & COUPLE_BOTH) || (tn % 2 == 1);
         if (fwd) {
             for (int p = threadIdx.x; p < a.n_pairs; p += blockDim.x) {
                 const PairDev pr = a.pairs[p];
@@ -404,12 +414,22 @@ __global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
                 const IoletDev &io = a.io[k];
                 if (io.pair_n == 0) continue;
                 double sum = 0.0;
-                for (int p = io.pair_lo; p < io.pair_lo + io.pair_n; ++p) {
-                    const PairDev pr = a.pairs[p];
-                    const double pv = (mr[pr.in_g] - RHO0) / 3.0;
-                    sum = sum + pv / (1.0 - pr.delta);
+                if (a.couple_mode & COUPLE_VEL) {
+                    // velocity-driven outlet: the mean over its veins of
+                    // mean_u(vein) / s, imposed as a peak of that over phibar
+                    for (int p = io.pair_lo; p < io.pair_lo + io.pair_n; ++p) {
+                        const PairDev pr = a.pairs[p];
+                        sum = sum + mu[pr.in_g] / pr.s;
+                    }
+                    a.held[k] = io.phibar > 0.0 ? (sum / (double)io.pair_n) / io.phibar : 0.0;
+                } else {
+                    for (int p = io.pair_lo; p < io.pair_lo + io.pair_n; ++p) {
+                        const PairDev pr = a.pairs[p];
+                        const double pv = (mr[pr.in_g] - RHO0) / 3.0;
+                        sum = sum + pv / (1.0 - pr.delta);
+                    }
+                    a.held[k] = RHO0 + 3.0 * (sum / (double)io.pair_n);
                 }
-                a.held[k] = RHO0 + 3.0 * (sum / (double)io.pair_n);
             }
         }
         __syncthreads();
@@ -470,7 +490,17 @@ __device__ __forceinline__ bool collide_site(R (&x)[Q], const SegDev &sg, R Fx, 
     return !isfinite(rho);
 }
 
-enum { M_BULK = 0, M_BND = 1, M_RAW = 2, M_FUSED = 3 };
+// M_FUSEDP: the fused launch whose bulk entries take two adjacent sites per lane
+enum { M_BULK = 0, M_BND = 1, M_RAW = 2, M_FUSED = 3, M_FUSEDP = 4 };
+
+// Storage forms with a two-sites-per-lane bulk path (the weight-normalised and
+// stochastic FP16 forms store through their own conversions).
+template <typename T>
+constexpr bool pair_ok() {
+    return std::is_same<T, double>::value || std::is_same<T, float>::value || std::is_same<T, __half>::value;
+}
+template <typename T>
+__device__ __forceinline__ void pair_sites(const KArgs &a, const Entry &e);
 
 // ---------------------------------------------------------------------------
 // The step kernel.  M_BULK / M_BND: pull step t -> t+1 over bulk or boundary
@@ -488,8 +518,19 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
     if (eidx < 0) return;  // uniform over the work-group
     const Entry e = a.entries[eidx];
     const int klass = tag_class(e.tag);
+    if constexpr (MODE == M_FUSEDP) {
+        // bulk entries of up to two work-groups' sites, two adjacent sites per lane
+        if (bulk_class(klass)) {
+            pair_sites<T>(a, e);
+            return;
+        }
+    }
     const SegDev &sg = a.seg[e.seg];
-    const int tid = threadIdx.x;
+    // one site per lane; the initialisation pass over a bulk entry of the
+    // two-sites-per-lane schedule (up to 2 x blockDim sites) takes two rounds
+    const int rounds = (MODE == M_RAW) ? (e.count + (int)blockDim.x - 1) / (int)blockDim.x : 1;
+    for (int round = 0; round < rounds; ++round) {
+    const int tid = (int)threadIdx.x + round * (int)blockDim.x;
     const bool act = tid < e.count;
     const int64_t s = (int64_t)e.start + tid;
 
@@ -499,7 +540,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
             const T *__restrict__ raw = lat_ptr<T>(a, t + 1);
 #pragma unroll
             for (int i = 0; i < Q; ++i) x[i] = ldc(raw + lidx(i, s), i);
-        } else if (MODE == M_FUSED) {
+        } else if (MODE == M_FUSED || MODE == M_FUSEDP) {
             if (bulk_class(klass))
                 gather<T, false>(a, e, sg, t, s, x);
             else
@@ -566,7 +607,7 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
             stc(lout + lidx(i, s), o, i, rkey<T>(lidx(i, s), tn));
         }
     }
-    if (__ballot(bad) != 0 && (tid & 63) == 0) a.ctrl->nan_flag = 1;
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) a.ctrl->nan_flag = 1;
 
     if (klass == K_IOLET) {
         const IoletDev &io = a.io[tag_iolet(e.tag)];
@@ -577,11 +618,12 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
         }
         const double su = block_sum(un, lds);
         const double sr = block_sum(rh, lds);
-        if (tid == 0) {
+        if (threadIdx.x == 0) {
             a.partials[2 * eidx] = su;
             a.partials[2 * eidx + 1] = sr;
         }
     }
+    }  // rounds
 }
 
 template <typename T, int MODE>
@@ -608,14 +650,13 @@ __device__ __forceinline__ float cvt(float v) { return v; }
 __device__ __forceinline__ float cvt(_Float16 v) { return (float)v; }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
+__device__ __forceinline__ void pair_sites(const KArgs &a, const Entry &e) {
     using R = typename Arith<T>::R;
     using V2 = typename Vec2<T>::type;
     using E = typename Vec2<T>::elem;
     constexpr bool OFF = Arith<T>::OFF;
     const int64_t t = a.ctrl->t;
     const int64_t tn = t + 1;
-    const Entry e = a.entries2[block_index(a.xcd_remap)];
     const SegDev &sg = a.seg[e.seg];
     const int base = 2 * (int)threadIdx.x;
     if (base >= e.count) return;
@@ -688,6 +729,11 @@ __global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_bulk2(KArgs a) {
+    pair_sites<T>(a, a.entries2[block_index(a.xcd_remap)]);
+}
+
 // The same kernel with the register budget of six waves per SIMD: used for the
 // FP32/FP16 boundary and fused variants, whose boundary path would otherwise
 // drop occupancy to five waves (FP64 would spill, so it keeps k_step).
@@ -698,6 +744,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
 
 template <typename T, int MODE>
 static void launch_mode(int grid, int block, hipStream_t st, const KArgs &a) {
+    if constexpr (MODE == M_FUSED && pair_ok<T>()) {
+        if (a.pair_fused) {
+            // the two-sites-per-lane bulk path in its own kernel, so that the
+            // plain fused kernel keeps its register budget
+            if constexpr (std::is_same<T, __half>::value)
+                hipLaunchKernelGGL((k_step_occ<T, M_FUSEDP>), dim3(grid), dim3(block), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_step<T, M_FUSEDP>), dim3(grid), dim3(block), 0, st, a);
+            return;
+        }
+    }
     if constexpr (MODE == M_BULK && !std::is_same<T, h16w>::value && !std::is_same<T, h16sr>::value) {
         if (a.n_pairs_blocks > 0) {
             hipLaunchKernelGGL((k_bulk2<T>), dim3(a.n_pairs_blocks), dim3(block), 0, st, a);
@@ -1021,9 +1078,11 @@ __global__ void __launch_bounds__(256) k_observe(KArgs a) {
     const int direct = a.ctrl->direct;
     const Entry e = a.entries[blockIdx.x];
     const SegDev &sg = a.seg[e.seg];
-    if ((int)threadIdx.x >= e.count) return;
-    const int64_t s = (int64_t)e.start + threadIdx.x;
-    if (s < a.obs_lo || s >= a.obs_hi) return;  // outside this pass's window
+    // one site per lane, in rounds when the entry holds more sites than lanes
+    // (bulk entries of the two-sites-per-lane schedule)
+    for (int k = threadIdx.x; k < e.count; k += blockDim.x) {
+    const int64_t s = (int64_t)e.start + k;
+    if (s < a.obs_lo || s >= a.obs_hi) continue;  // outside this pass's window
     const int64_t N = a.N;
     R x[Q];
     if (a.aa) {
@@ -1093,6 +1152,7 @@ __global__ void __launch_bounds__(256) k_observe(KArgs a) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) a.fout[(size_t)i * N + s] = f[i];
     }
+    }  // sites
 }
 
 // Full f(t) (double) -> raw storage in lat[(t+1)&1].

@@ -89,8 +89,8 @@ SegDev seg_of(const Domain &d) {
     return s;
 }
 
-int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint64_t order_flags, Layout &L,
-                std::string &err) {
+int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint64_t order_flags, int couple_mode,
+                Layout &L, std::string &err) {
     L = Layout{};
     int64_t total = 0;
     for (auto &d : doms) total += d.n;
@@ -349,7 +349,7 @@ int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint
                     for (int a = 0; a < 3; ++a) L.bnrm[(size_t)a * Nb + b] = nv[a] / nl;
             }
             const int32_t k = cls[d][x];
-            if (k >= 0 && dm.io[k].kind == KIND_INLET) {
+            if (k >= 0 && velocity_driven(dm.io[k], couple_mode)) {
                 const IoletH &io = dm.io[k];
                 double dv[3], dn = 0.0, dd = 0.0;
                 for (int a = 0; a < 3; ++a) {
@@ -378,7 +378,7 @@ int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint
                 io.a[m] = ih.wave.a[m];
                 io.b[m] = ih.wave.b[m];
             }
-            io.kind = ih.kind;
+            io.kind = velocity_driven(ih, couple_mode) ? KIND_INLET : KIND_OUTLET;
             io.coupled = ih.coupled ? 1 : 0;
             io.seg = d;
         }
@@ -475,16 +475,19 @@ void plan_xcd_bricks(Layout &L, int run) {
 // the interleaved layout a chunk of a mixed range goes to the bulk kernel
 // when none of its sites has a boundary link.  The fused schedule keeps every
 // entry in storage order for a single launch (n_bulk_blocks = 0).
-void plan_schedule(Layout &L, int block, int sched_flags) {
+void plan_schedule(Layout &L, int block, int sched_flags, bool pair_bulk) {
     std::vector<Entry> bulk, bnd;
     std::vector<int32_t> rbulk, rbnd;
     for (auto &io : L.hio) io.e_lo = io.e_hi = 0;
+    const bool fused_pairs = pair_bulk && (sched_flags & HL_SCHED_FUSED) && (sched_flags & HL_SCHED_PAIRS);
+    L.bulk_chunk = fused_pairs ? 2 * block : block;
     for (size_t r = 0; r < L.ranges.size(); ++r) {
         const Range &g = L.ranges[r];
-        for (int64_t off = 0; off < g.count; off += block) {
+        const int chunk = (!g.mixed && (g.tag == K_BULK || g.tag == K_NEAR)) ? L.bulk_chunk : block;
+        for (int64_t off = 0; off < g.count; off += chunk) {
             Entry e;
             e.start = (int32_t)(g.start + off);
-            e.count = (int32_t)std::min<int64_t>(block, g.count - off);
+            e.count = (int32_t)std::min<int64_t>(chunk, g.count - off);
             e.seg = g.seg;
             e.tag = g.tag;
             if (g.mixed) {
@@ -575,9 +578,12 @@ int check_layout(const std::vector<Domain> &doms, const Layout &L, int block, st
     std::vector<int8_t> seen((size_t)N, 0);
     for (size_t e = 0; e < L.entries.size(); ++e) {
         const Entry &en = L.entries[e];
-        if (en.count < 1 || en.count > block || en.start < 0 || (int64_t)en.start + en.count > N)
-            return failf(err, HL_E_RANGE, "entry %zu covers [%d, %d)", e, en.start, en.start + en.count);
         const int k = tag_class(en.tag);
+        const int most = (k == K_BULK || k == K_NEAR) ? std::max(block, L.bulk_chunk) : block;
+        if (en.count < 1 || en.count > most || en.start < 0 || (int64_t)en.start + en.count > N)
+            return failf(err, HL_E_RANGE, "entry %zu covers [%d, %d)", e, en.start, en.start + en.count);
+        if (most > block && (en.start & 1))
+            return failf(err, HL_E_INVAL, "two-sites-per-lane entry %zu starts on an odd site", e);
         for (int32_t s = en.start; s < en.start + en.count; ++s) {
             if (seen[s]) return failf(err, HL_E_INVAL, "site %d is in two entries", s);
             seen[s] = 1;

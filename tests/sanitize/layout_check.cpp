@@ -90,19 +90,21 @@ int main(int argc, char **argv) {
                           HL_SCHED_XCD_REMAP,
                           HL_SCHED_XCD_REMAP | HL_SCHED_XCD_RUNS | HL_SCHED_FUSED,
                           HL_SCHED_PAIRS,
-                          HL_SCHED_FUSED | HL_SCHED_XCD_BRICKS};
+                          HL_SCHED_FUSED | HL_SCHED_XCD_BRICKS,
+                          HL_SCHED_FUSED | HL_SCHED_PAIRS | HL_SCHED_XCD_REMAP | HL_SCHED_XCD_RUNS,
+                          HL_SCHED_FUSED | HL_SCHED_PAIRS | HL_SCHED_XCD_BRICKS};
     int plans = 0;
     for (uint64_t o : orders) {
         hl::Layout L;
         std::string err;
         std::vector<hl::Domain> dd = doms;
-        if (hl::plan_layout(dd, pairs, o, L, err) != HL_OK) {
+        if (hl::plan_layout(dd, pairs, o, (o & HL_ORDER_BRICK) ? HL_COUPLE_VELOCITY : 0, L, err) != HL_OK) {
             fprintf(stderr, "plan_layout(order %llu): %s\n", (unsigned long long)o, err.c_str());
             return 1;
         }
         for (int s : scheds)
             for (int block : {64, 128, 256}) {
-                hl::plan_schedule(L, block, s);
+                hl::plan_schedule(L, block, s, true);
                 if ((s & HL_SCHED_XCD_BRICKS) && (o & HL_ORDER_BRICK) && L.emap.empty()) {
                     fprintf(stderr, "no XCD map for order %llu\n", (unsigned long long)o);
                     return 1;

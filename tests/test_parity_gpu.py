@@ -110,6 +110,40 @@ def test_coupled_1to3_fp64(hl, oracle_mod, mode):
         np.testing.assert_allclose(g.iolet_bc(d, which=1), o.last_bc(d), rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("order", [0, 16, 16 | 8])
+def test_velocity_reverse_coupling_fp64(hl, oracle_mod, order, mode=2, steps=61):
+    """HL_COUPLE_VELOCITY, the second reading of the reverse exchange: each
+    coupled arterial outlet becomes a velocity (Ladd) boundary whose site mean
+    is the mean over its veins of mean_u(vein) / s.  The 1:3 tubes, alternating
+    directions, two lattices and in place: FP64 matches the oracle's
+    velocity-reverse mode in both domains, boundary values included.  The
+    reading has no pressure feedback and amplifies any difference, round-off
+    included, so the comparison is made before that growth (61 steps; with
+    both directions every step a 1e-16 perturbation of the oracle alone grows
+    to 2e-11 in the same time, so that combination, whose two halves are each
+    covered by the other coupling tests, is not compared)."""
+    art = synth.tubes(1, radius=4.0, length=24)
+    ven = synth.tubes(3, radius=4.0, length=24)
+    dp = [0.30, 0.52, 0.69]
+    s = oracle_mod.velocity_factors(dp, [1.0, 0.6156, 0.5639], [1, 1, 1], 1.0)
+    sc = Scenario([Dom(art, tau=0.8, inlets={0: (0.01, (), (), 1.0)}),
+                   Dom(ven, tau=0.8)],
+                  pairs=[(0, 1, 1, i, float(s[i]), dp[i]) for i in range(3)], mode=mode)
+    o = build_oracle(sc, oracle_mod)
+    g = build_gpu(sc, hl, "f64", order=order)
+    o.step(steps)
+    g.step(steps)
+    for d in (0, 1):
+        err = errors(g, o, d)
+        print("velocity reverse", mode, order, d, err, flush=True)
+        check64(err)
+        np.testing.assert_allclose(g.iolet_bc(d, which=1), o.last_bc(d), rtol=1e-12, atol=1e-15)
+    assert 0.0 < abs(g.iolet_bc(0, which=1)[1]) < 0.1    # a velocity, not a density near 1
+    with pytest.raises(hl.HLError):
+        bad = hl.Context(0, "f64")
+        bad.set_coupling_mode(8)
+
+
 # Errors of the reduced-precision storage forms against the FP64 oracle on the
 # cylinder after 1000 steps (two lattices and in place), measured on the
 # MI355X; each bound is about four times the larger of the two measurements,
@@ -317,7 +351,7 @@ def test_autotune_keeps_state(hl):
     blk, flags = a.schedule()
     assert blk in (64, 128, 256)
     n, best, second, spread = a.autotune_report()
-    assert n == 30                      # 3 sizes x (9 + the brick-aligned XCD runs)
+    assert n == 36                      # 3 sizes x (10 + the brick-aligned XCD runs, with and without pairs)
     assert 0.0 < best <= second and spread >= 0.0
     a.step(5)
     b = build_gpu(cylinder_scenario(nz=24), hl, order=hl.HL_ORDER_BRICK)
@@ -412,6 +446,33 @@ def test_xcd_runs_schedule(hl, oracle_mod, order, sched):
         # through int16 deltas
         assert 0 < inf["n_near"] < inf["n_sites"]
     check64(errors(g, o))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("order", [2, 8 | 32])
+def test_fused_pairs_match(hl, oracle_mod, prec, order):
+    """The fused launch with two adjacent sites per lane on its bulk work-groups
+    (int32 indices, or int16 deltas in the brick layout; with and without XCD
+    order) performs the same arithmetic as the one-site fused launch, so the
+    states agree bit for bit; FP64 also matches the oracle, with the layout
+    checked exhaustively on the host (HL_DEBUG_CHECKS)."""
+    geo = synth.tree_geometry(3, 7.0, 20100416, lam=6.0)
+    outs = {k: (1.0, (), (), 1.0) for k in range(1, len(geo.iolets))}
+    sc = Scenario([Dom(geo, tau=0.6, bouzidi=True, inlets={0: (0.01, (), (), 1.0)}, outlets=outs)])
+    F, P = hl.HL_SCHED_FUSED, hl.HL_SCHED_PAIRS
+    xcd = hl.HL_SCHED_XCD_BRICKS if order & 8 else hl.HL_SCHED_XCD_REMAP | hl.HL_SCHED_XCD_RUNS
+    res = []
+    for flags in (F, F | P, F | P | xcd):
+        g = build_gpu(sc, hl, prec, order=order | hl.HL_DEBUG_CHECKS)
+        g.set_schedule(128, flags)
+        g.step(61)
+        res.append(g.populations(0))
+        if prec == "f64" and flags != F:
+            o = build_oracle(sc, oracle_mod)
+            o.step(61)
+            check64(errors(g, o))
+        g.close()
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])
