@@ -192,6 +192,7 @@ hl::KArgs make_args(hl_ctx *c) {
     a.n_emap = (int32_t)c->L.emap.size();
     a.ctrl = c->d_ctrl;
     a.aa = c->aa ? 1 : 0;
+    a.dt = 0;
     a.partials = c->d_partials;
     a.stats = c->d_stats;
     a.bc = c->d_bc;
@@ -237,17 +238,28 @@ int upload_schedule(hl_ctx *c) {
 
 // n steps as plain launches; t0 is the step counter before the first one (the
 // in-place scheme alternates its even and odd kernels).
+// (Launch k of the batch works on step t0 + k through its dt; the stored
+// counter advances once after the batch.  The per-step finalize kernel runs
+// only when the context couples domains.)
 int launch_steps_plain(hl_ctx *c, int64_t n, hipStream_t st, int64_t t0) {
-    const hl::KArgs a = make_args(c);
+    if (n <= 0) return HL_OK;
+    hl::KArgs a = make_args(c);
     const bool fused = (c->sched_flags & HL_SCHED_FUSED) != 0;
     for (int64_t k = 0; k < n; ++k) {
+        a.dt = (int32_t)k;
         int e = c->aa ? hl::launch_aa_step(c->precision, a, c->L.n_bulk_blocks, c->L.n_bnd_blocks, c->block, st, 0, fused,
                                            (int)((t0 + k) & 1))
                       : hl::launch_step(c->precision, a, c->L.n_bulk_blocks, c->L.n_bnd_blocks, c->block, st, 0, fused);
         if (e != 0) return fail(c, HL_E_DEVICE, "step launch failed: %s", hipGetErrorString((hipError_t)e));
     }
+    a.dt = 0;
+    int e = hl::launch_advance(a, n, st);
+    if (e != 0) return fail(c, HL_E_DEVICE, "advance launch failed: %s", hipGetErrorString((hipError_t)e));
     return HL_OK;
 }
+
+// Steps of a batch longer than this go in several launches sequences (dt is int32).
+constexpr int64_t MAX_BATCH = (int64_t)1 << 30;
 
 int ensure_graph(hl_ctx *c) {
     if (c->gexec && c->graph_steps == c->steps_per_graph) return HL_OK;
@@ -271,6 +283,7 @@ int ensure_graph(hl_ctx *c) {
 }
 
 int run_steps(hl_ctx *c, int64_t n) {
+    if (n <= 0) return HL_OK;  // keeps the means of the current step valid
     int64_t rest = n, t = c->t_host;
     if (c->aa && (c->steps_per_graph & 1)) c->steps_per_graph *= 2;  // graphs keep the sweep parity
     if (c->drive == HL_DRIVE_GRAPH && n >= c->steps_per_graph + (t & 1)) {
@@ -288,11 +301,18 @@ int run_steps(hl_ctx *c, int64_t n) {
             t += c->graph_steps;
         }
     }
-    int rc = launch_steps_plain(c, rest, c->stream, t);
-    if (rc != HL_OK) return rc;
+    while (rest > 0) {
+        const int64_t m = std::min(rest, MAX_BATCH);
+        int rc = launch_steps_plain(c, m, c->stream, t);
+        if (rc != HL_OK) return rc;
+        rest -= m;
+        t += m;
+    }
     c->t_host += n;
     c->obs_t = -1;
-    c->stats_t = c->aa ? c->t_host - 1 : c->t_host;
+    // coupled contexts finalize every step; the others compute their iolet
+    // means on demand
+    c->stats_t = c->L.hpairs.empty() ? -1 : (c->aa ? c->t_host - 1 : c->t_host);
     HIPC(c, hipMemcpyAsync(c->h_nan, &c->d_ctrl->nan_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     return HL_OK;
 }
@@ -371,13 +391,17 @@ int reinit(hl_ctx *c) {
     return HL_OK;
 }
 
-// The in-place scheme reduces f(t) during the sweep t -> t+1; a read of the
-// iolet means or boundary values of the current step runs the moments pass
-// (idempotent: the next sweep recomputes the same values).
+// Iolet means and boundary values of the current step, when the last steps
+// did not leave them: the in-place scheme reduces f(t) during the sweep
+// t -> t+1, so it runs the moments pass (idempotent: the next sweep
+// recomputes the same values); two lattices reduce f(t) in the step that
+// produces it, so the partial sums of the last step only need the finalize.
 int ensure_stats(hl_ctx *c) {
     if (c->stats_t == c->t_host) return HL_OK;
     hl::KArgs a = make_args(c);
-    int e = hl::launch_aa_moments(c->precision, a, (int)c->L.entries.size(), c->block, c->stream, (int)(c->t_host & 1));
+    int e = c->aa ? hl::launch_aa_moments(c->precision, a, (int)c->L.entries.size(), c->block, c->stream,
+                                          (int)(c->t_host & 1))
+                  : hl::launch_stats(a, c->stream);
     if (e != 0) return fail(c, HL_E_DEVICE, "moments launch failed: %s", hipGetErrorString((hipError_t)e));
     c->stats_t = c->t_host;
     return HL_OK;
@@ -855,7 +879,7 @@ int hl_read_iolet_stats(hl_ctx *ctx, int32_t dom, double *mean_u, double *mean_p
     if (d.n_iolet == 0) return HL_OK;
     if (!mean_u || !mean_p) return fail(ctx, HL_E_INVAL, "NULL output");
     HIPC(ctx, hipSetDevice(ctx->device));
-    if (ctx->aa && (rc = ensure_stats(ctx)) != HL_OK) return rc;
+    if ((rc = ensure_stats(ctx)) != HL_OK) return rc;
     const size_t nio = ctx->L.hio.size();
     std::vector<double> st(2 * nio);
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
@@ -877,7 +901,7 @@ int hl_read_iolet_bc(hl_ctx *ctx, int32_t dom, int which, double *out) {
     if (d.n_iolet == 0) return HL_OK;
     if (!out) return fail(ctx, HL_E_INVAL, "NULL output");
     HIPC(ctx, hipSetDevice(ctx->device));
-    if (ctx->aa && which == 0 && (rc = ensure_stats(ctx)) != HL_OK) return rc;
+    if ((rc = ensure_stats(ctx)) != HL_OK) return rc;
     const size_t nio = ctx->L.hio.size();
     std::vector<double> bc(2 * nio);
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
@@ -955,6 +979,7 @@ int hl_get_state(hl_ctx *ctx, void *buf, size_t *bytes) {
     if (*bytes < need) return fail(ctx, HL_E_INVAL, "state buffer holds %zu of %zu bytes", *bytes, need);
     *bytes = need;
     HIPC(ctx, hipSetDevice(ctx->device));
+    if ((rc = ensure_stats(ctx)) != HL_OK) return rc;  // the saved means and values are those of step t
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     char *p = (char *)buf;
     StateHeader h{};
@@ -1024,7 +1049,7 @@ int hl_set_state(hl_ctx *ctx, const void *buf, size_t bytes) {
     ctx->t_host = ctrl.t;
     *ctx->h_nan = ctrl.nan_flag;
     ctx->obs_t = -1;
-    ctx->stats_t = ctx->aa ? -1 : ctx->t_host;
+    ctx->stats_t = ctx->t_host;
     return HL_OK;
 }
 
@@ -1054,6 +1079,8 @@ int hl_set_schedule(hl_ctx *ctx, int32_t block_size, int32_t flags) {
     ctx->sched_flags = flags;
     if (!ctx->committed) return HL_OK;
     HIPC(ctx, hipSetDevice(ctx->device));
+    int rc;
+    if (rebuild && (rc = ensure_stats(ctx)) != HL_OK) return rc;  // from the partials about to be replaced
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     if (rebuild) {
         hl::plan_schedule(ctx->L, ctx->block, ctx->sched_flags, pairs_supported(ctx));
@@ -1214,10 +1241,11 @@ int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd
     HIPC(ctx, hipSetDevice(ctx->device));
     std::vector<hipEvent_t> ev((size_t)3 * nsteps, nullptr);
     for (auto &e : ev) HIPC(ctx, hipEventCreate(&e));
-    const hl::KArgs a = make_args(ctx);
+    hl::KArgs a = make_args(ctx);
     const bool fu = (ctx->sched_flags & HL_SCHED_FUSED) != 0;
     int err = 0;
     auto part = [&](int64_t k, int which) {
+        a.dt = (int32_t)k;
         const int odd = (int)((ctx->t_host + k) & 1);
         return ctx->aa ? hl::launch_aa_step(ctx->precision, a, ctx->L.n_bulk_blocks, ctx->L.n_bnd_blocks, ctx->block,
                                             ctx->stream, which, fu, odd)
@@ -1232,6 +1260,8 @@ int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd
         HIPC(ctx, hipEventRecord(ev[3 * k + 2], ctx->stream));
         if (!err) err = part(k, 3);
     }
+    a.dt = 0;
+    if (!err) err = hl::launch_advance(a, nsteps, ctx->stream);
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     double sb = 0.0, sn = 0.0;
     for (int64_t k = 0; k < nsteps; ++k) {
@@ -1245,7 +1275,7 @@ int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd
     if (err) return fail(ctx, HL_E_DEVICE, "step launch failed: %s", hipGetErrorString((hipError_t)err));
     ctx->t_host += nsteps;
     ctx->obs_t = -1;
-    ctx->stats_t = ctx->aa ? ctx->t_host - 1 : ctx->t_host;
+    ctx->stats_t = ctx->L.hpairs.empty() ? -1 : (ctx->aa ? ctx->t_host - 1 : ctx->t_host);
     *ms_bulk = sb / (double)nsteps;
     *ms_bnd = sn / (double)nsteps;
     return HL_OK;

@@ -103,6 +103,7 @@ struct KArgs {
     int32_t couple_mode, xcd_remap;  // xcd_remap: 0 none, 1 contiguous eighths, C > 1 runs of C entries
     const Entry *entries2;   // bulk entries of 2 x block sites (two sites per lane)
     int32_t aa;              // 1: one in-place lattice (lat0), AA-pattern sweeps
+    int32_t dt;              // steps since the stored counter: a launch works on step ctrl->t + dt
     int32_t n_pairs_blocks;  // > 0: the bulk launch runs the two-sites-per-lane kernel
     int32_t pair_fused;      // 1: fused launch whose bulk entries hold up to 2 x block sites, two per lane
     int32_t io_e0, io_e1;    // entry span covering every iolet's entries (empty: io_e0 == io_e1)
@@ -127,6 +128,12 @@ struct KArgs {
 int launch_step(int prec, const KArgs &a, int n_bulk, int n_bnd, int block, void *stream, int part = 0,
                 bool fused = false);
 int launch_init(int prec, const KArgs &a, int n_entries, int block, void *stream);
+// After a batch of n steps launched with dt = 0 .. n-1: advance the stored step
+// counter by n (one work-item).
+int launch_advance(const KArgs &a, int64_t n, void *stream);
+// Iolet means and boundary values of the current step from the partial sums
+// of the last step (two lattices; contexts whose steps skip the finalize).
+int launch_stats(const KArgs &a, void *stream);
 int launch_observe(int prec, const KArgs &a, int n_entries, int block, void *stream);
 int launch_load_raw(int prec, const KArgs &a, void *stream);
 int launch_fill_rest(int prec, const KArgs &a, void *stream);

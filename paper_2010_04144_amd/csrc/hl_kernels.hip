@@ -218,6 +218,10 @@ __device__ __forceinline__ int entry_index(const KArgs &a) {
     return a.e_off + block_index(a.xcd_remap);
 }
 
+// Step of a launch: the stored counter plus the launch's offset in its batch
+// (the counter is advanced once per batch).
+__device__ __forceinline__ int64_t step_time(const KArgs &a) { return a.ctrl->t + a.dt; }
+
 // ---------------------------------------------------------------------------
 // Step 1-2: the populations f_j(x, p+1) of site s, streamed from f*(p).
 // BND selects the boundary path (pull codes may be negative).
@@ -346,22 +350,36 @@ __device__ double series_at(const IoletDev &io, int64_t t) {
     return v;
 }
 
+// Boundary values of the iolets without coupling for the stream tn -> tn+1,
+// written by the first work-group of a step's boundary (or fused) launch.
+// The launch itself reads the other parity, so the write races with nothing.
+__device__ __forceinline__ void publish_series(const KArgs &a, int64_t tn) {
+    if (blockIdx.x != 0) return;
+    for (int k = threadIdx.x; k < a.n_io; k += blockDim.x) {
+        const IoletDev &io = a.io[k];
+        if (!io.coupled) a.bc[(tn & 1) * a.n_io + k] = series_at(io, tn);
+    }
+}
+
 // One work-group after the site kernels of a step (stream order, no
 // fences): iolet means of f(tn) from the per-work-group partial sums,
-// coupling, boundary values for the stream tn -> tn+1, then publish tn.
-// raw = 1 after a (re)initialisation, where tn = t.
-// mode: FIN_STEP (two-lattice step: f(t+1) was reduced; t := t+1),
-// FIN_RAW (two-lattice reinitialisation: f(t) reduced; t kept; direct := 1),
-// FIN_AA_SWEEP (in-place sweep: f(t) reduced; t := t+1),
-// FIN_AA_MOMENTS (moments-only pass: f(t) reduced; t kept).
-enum { FIN_STEP = 0, FIN_RAW = 1, FIN_AA_SWEEP = 2, FIN_AA_MOMENTS = 3 };
+// coupling, boundary values for the stream tn -> tn+1.  t is the launch's
+// step (stored counter + dt); the stored counter itself is advanced by
+// k_advance once per batch.  Contexts without coupling run it only on demand
+// (their steps publish the boundary series themselves).
+// mode: FIN_STEP (two-lattice step: f(t+1) was reduced; tn = t+1),
+// FIN_RAW (two-lattice reinitialisation: f(t) reduced; tn = t; direct := 1),
+// FIN_AA_SWEEP (in-place sweep: f(t) reduced; tn = t),
+// FIN_AA_MOMENTS (moments-only pass: f(t) reduced; tn = t),
+// FIN_STATS (two lattices, on demand: the last step reduced f(t); tn = t).
+enum { FIN_STEP = 0, FIN_RAW = 1, FIN_AA_SWEEP = 2, FIN_AA_MOMENTS = 3, FIN_STATS = 4 };
 
 // Partial sums staged per pass of the iolet sums (16 B each).
 constexpr int FIN_CHUNK = 2048;
 
 __global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
     __shared__ double2 stage[FIN_CHUNK];
-    const int64_t t = a.ctrl->t;
+    const int64_t t = step_time(a);
     const int64_t tn = (mode == FIN_STEP) ? t + 1 : t;
     double *mu = a.stats;
     double *mr = a.stats + a.n_io;
@@ -436,15 +454,15 @@ __global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
         for (int k = threadIdx.x; k < a.n_io; k += blockDim.x)
             if (a.io[k].coupled) a.bc[(tn & 1) * a.n_io + k] = a.held[k];
     }
-    __syncthreads();  // every thread has read ctrl->t
-    if (threadIdx.x == 0) {
-        if (mode == FIN_STEP || mode == FIN_RAW) {
-            a.ctrl->direct = (mode == FIN_RAW);
-            a.ctrl->t = tn;
-        } else if (mode == FIN_AA_SWEEP) {
-            a.ctrl->direct = 0;
-            a.ctrl->t = t + 1;
-        }
+    if (mode == FIN_RAW && threadIdx.x == 0) a.ctrl->direct = 1;
+}
+
+// The stored step counter after a batch of n steps; a reloaded lattice is no
+// longer the raw state.
+__global__ void k_advance(KArgs a, int64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        a.ctrl->t += n;
+        a.ctrl->direct = 0;
     }
 }
 
@@ -512,8 +530,9 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     __shared__ double lds[8];
-    const int64_t t = a.ctrl->t;
+    const int64_t t = step_time(a);
     const int64_t tn = (MODE == M_RAW) ? t : t + 1;
+    if constexpr (MODE == M_BND || MODE == M_FUSED || MODE == M_FUSEDP) publish_series(a, tn);
     const int eidx = entry_index(a);
     if (eidx < 0) return;  // uniform over the work-group
     const Entry e = a.entries[eidx];
@@ -655,7 +674,7 @@ __device__ __forceinline__ void pair_sites(const KArgs &a, const Entry &e) {
     using V2 = typename Vec2<T>::type;
     using E = typename Vec2<T>::elem;
     constexpr bool OFF = Arith<T>::OFF;
-    const int64_t t = a.ctrl->t;
+    const int64_t t = step_time(a);
     const int64_t tn = t + 1;
     const SegDev &sg = a.seg[e.seg];
     const int base = 2 * (int)threadIdx.x;
@@ -941,8 +960,11 @@ __device__ __forceinline__ void aa_sweep_body(const KArgs &a) {
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     __shared__ double lds[8];
-    const int64_t t = a.ctrl->t;
-    const int direct = a.ctrl->direct;
+    const int64_t t = step_time(a);
+    // the raw (reloaded) state is seen only by the first sweep of a batch
+    const int direct = a.dt == 0 ? a.ctrl->direct : 0;
+    // the sweep reads the values of step t-1 and publishes those of step t
+    if constexpr (MODE != M_BULK) publish_series(a, t);
     const int eidx = entry_index(a);
     if (eidx < 0) return;  // uniform over the work-group
     const Entry e = a.entries[eidx];
@@ -1271,7 +1293,8 @@ static int step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStream_t
             launch_mode<T, M_BND>(n_bnd, block, st, a);
         }
     }
-    if (part == 0 || part == 3) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_STEP);
+    if ((part == 0 || part == 3) && a.n_pairs > 0)
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_STEP);
     return (int)hipGetLastError();
 }
 
@@ -1283,6 +1306,18 @@ static int init_t(const KArgs &a0, int n_entries, int block, hipStream_t st) {
     a.emap = nullptr;  // one work-group per entry, in entry order
     hipLaunchKernelGGL((k_step<T, M_RAW>), dim3(n_entries), dim3(block), 0, st, a);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_RAW);
+    return (int)hipGetLastError();
+}
+
+int launch_advance(const KArgs &a, int64_t n, void *stream) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, (hipStream_t)stream, a, n);
+    return (int)hipGetLastError();
+}
+
+int launch_stats(const KArgs &a0, void *stream) {
+    KArgs a = a0;
+    a.dt = 0;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, (hipStream_t)stream, a, (int)FIN_STATS);
     return (int)hipGetLastError();
 }
 
@@ -1349,7 +1384,8 @@ static int aa_step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStrea
             launch_aa_mode<T, M_BND, ODD>(n_bnd, block, st, a);
         }
     }
-    if (part == 0 || part == 3) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_AA_SWEEP);
+    if ((part == 0 || part == 3) && a.n_pairs > 0)
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, (int)FIN_AA_SWEEP);
     return (int)hipGetLastError();
 }
 

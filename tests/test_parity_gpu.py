@@ -83,6 +83,38 @@ def test_pulsatile_inlet_outlet_series_and_force(hl, oracle_mod):
     np.testing.assert_allclose(g.iolet_bc(0, which=1), o.last_bc(0), rtol=1e-13, atol=1e-15)
 
 
+@pytest.mark.parametrize("order,sched", [(0, 0), (40, 11), (16, 0), (16 | 8 | 32, 3)])
+def test_series_change_between_steps(hl, oracle_mod, order, sched):
+    """New inlet and outlet series set between steps apply from the next step
+    on: the observables and iolet means of the current step, and the boundary
+    values the last step used, keep the old series.  Two lattices and the
+    in-place scheme; without coupling the steps publish their own boundary
+    values and the means are reduced on demand."""
+    geo = synth.tubes(2, radius=4.0, length=20)
+    sc = Scenario([Dom(geo, tau=0.7, inlets={0: (0.008, (0.002,), (0.001,), 60.0), 1: (0.004, (), (), 1.0)},
+                       outlets={2: (1.0, (0.0005,), (0.0002,), 80.0), 3: (1.0, (), (), 1.0)})])
+    o = build_oracle(sc, oracle_mod)
+    g = build_gpu(sc, hl, "f64", order=order)
+    g.set_schedule(128, sched)
+    o.step(37)
+    g.step(20)
+    g.step(17)
+    new_in = (0.006, (-0.001, 0.0015), (0.0005, 0.0), 50.0)
+    new_out = (1.0005, (0.0003,), (-0.0001,), 70.0)
+    io_in, io_out = geo.iolets[0], geo.iolets[2]
+    o.set_iolet(0, 0, oracle_mod.INLET, io_in.centre, io_in.normal, io_in.radius, *new_in)
+    o.set_iolet(0, 2, oracle_mod.OUTLET, io_out.centre, io_out.normal, io_out.radius, *new_out)
+    g.set_inlet_velocity(0, 0, *new_in)
+    g.set_outlet_density(0, 2, *new_out)
+    check64(errors(g, o))
+    np.testing.assert_allclose(g.iolet_bc(0, which=1), o.last_bc(0), rtol=1e-13, atol=1e-15)
+    o.step(31)
+    g.step(31)
+    g.step(0)
+    check64(errors(g, o))
+    np.testing.assert_allclose(g.iolet_bc(0, which=1), o.last_bc(0), rtol=1e-13, atol=1e-15)
+
+
 def test_periodic_womersley_pipe_fp64(hl, oracle_mod):
     geo = synth.cylinder(nz=4, ends="periodic")
     sc = Scenario([Dom(geo, tau=0.8, F0=(0.0, 0.0, 1e-5), omega=0.025)])
