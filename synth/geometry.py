@@ -224,8 +224,9 @@ class _SlabIndex:
         return out
 
 
-def build_site_list(x, y, z, dims, periodic=(False, False, False), iolets=(), meta=None):
-    """Number fluid voxels (in the given order) and build the neighbour table."""
+def build_site_list(x, y, z, dims, periodic=(False, False, False), iolets=(), meta=None, progress=None):
+    """Number fluid voxels (in the given order) and build the neighbour table.
+    progress(msg), when given, is called after every sixth direction."""
     x = np.ascontiguousarray(x, dtype=np.int64)
     y = np.ascontiguousarray(y, dtype=np.int64)
     z = np.ascontiguousarray(z, dtype=np.int64)
@@ -251,6 +252,8 @@ def build_site_list(x, y, z, dims, periodic=(False, False, False), iolets=(), me
         if miss.size:
             j[miss] = slabs.classify(xx[miss], yy[miss], zz[miss])
         nbr[i] = j
+        if progress is not None and i % 6 == 0:
+            progress(f"neighbour table: {i}/{NDIR - 1} directions of {n} sites")
     _one_iolet_per_site(nbr)
     coords = np.stack([x, y, z]).astype(np.int32)
     return Geometry(coords, nbr, list(iolets), dims, meta=dict(meta or {}))

@@ -97,13 +97,14 @@ def fit_lambda(depth, r0, seed, box, margin=4, radius_scale=1.0, lo=1.0, hi=60.0
     return lo
 
 
-def _voxelise(segs, dims, chunk=32):
+def _voxelise(segs, dims, chunk=32, progress=None):
     """Integer voxels inside the union of the segments (flat ends at open
-    ends, a sphere of the parent's radius at every internal joint)."""
+    ends, a sphere of the parent's radius at every internal joint).
+    progress(msg), when given, is called after every 16 segments."""
     parts = []
     nx, ny, nz = dims
     half_diag = 0.5 * chunk * np.sqrt(3.0)
-    for s in segs:
+    for k_seg, s in enumerate(segs):
         a = s.p1 - s.p0
         L = np.linalg.norm(a)
         a = a / L
@@ -135,6 +136,8 @@ def _voxelise(segs, dims, chunk=32):
                         m |= ex * ex + ey * ey + ez * ez < r2
                     if m.any():
                         parts.append(((vz[m].astype(np.int64) * ny + vy[m]) * nx + vx[m]))
+        if progress is not None and ((k_seg + 1) % 16 == 0 or k_seg + 1 == len(segs)):
+            progress(f"voxelised {k_seg + 1}/{len(segs)} segments")
     lin = np.unique(np.concatenate(parts)) if parts else np.zeros(0, np.int64)
     x = lin % nx
     y = (lin // nx) % ny
@@ -143,11 +146,12 @@ def _voxelise(segs, dims, chunk=32):
 
 
 def tree_geometry(depth, r0, seed, lam=None, box=None, margin=4, radius_scale=1.0,
-                  mirror=False, venous=False, q="random", q_seed=None, **kw):
+                  mirror=False, venous=False, q="random", q_seed=None, progress=None, **kw):
     """Voxelised tree.  Arterial trees have one velocity inlet at the root and
     a pressure outlet at every leaf; ``venous`` trees are the reverse (one
     inlet per leaf, a pressure outlet at the root).  Iolet 0 is the root,
-    iolets 1.. are the leaves in breadth-first order."""
+    iolets 1.. are the leaves in breadth-first order.  progress(msg), when
+    given, reports the voxelisation and the neighbour table as they go."""
     if lam is None:
         lam = fit_lambda(depth, r0, seed, box, margin, radius_scale, **kw)
     segs = tree_segments(depth, r0, lam, seed, radius_scale, mirror, **kw)
@@ -158,7 +162,7 @@ def tree_geometry(depth, r0, seed, lam=None, box=None, margin=4, radius_scale=1.
         s.p1 = s.p1 + shift
     ext = np.ceil(hi - lo).astype(np.int64) + 2 * margin
     dims = (int(box),) * 3 if box else tuple(int(v) for v in ext)
-    x, y, z = _voxelise(segs, dims)
+    x, y, z = _voxelise(segs, dims, progress=progress)
     root = segs[0]
     ra = (root.p1 - root.p0) / np.linalg.norm(root.p1 - root.p0)
     iolets = [Iolet(OUTLET if venous else INLET, root.p0.copy(), (-ra if venous else ra), root.r)]
@@ -169,7 +173,7 @@ def tree_geometry(depth, r0, seed, lam=None, box=None, margin=4, radius_scale=1.
     g = build_site_list(x, y, z, dims, (False, False, False), iolets,
                         meta=dict(kind="tree", depth=depth, r0=r0, lam=float(lam), seed=seed,
                                   radius_scale=radius_scale, venous=venous, n_leaves=len(leaves),
-                                  fill=float(x.size) / float(np.prod(dims))))
+                                  fill=float(x.size) / float(np.prod(dims))), progress=progress)
     if q == "random":
         g = g.with_q("random", seed=seed + 7 if q_seed is None else q_seed)
     return g

@@ -78,16 +78,23 @@ def pulsatile(rng, mean=0.01, spread=0.003, harmonics=3, period=None):
     return (mean, tuple(a), tuple(b), T)
 
 
+_JOB_PROGRESS = None  # progress(msg) of the tree jobs, set before the workers fork
+
+
 def _tree_job(job):
     depth, r0, seed, kw = job
-    return tree_geometry(depth, r0, seed, **kw)
+    return tree_geometry(depth, r0, seed, progress=_JOB_PROGRESS, **kw)
 
 
-def build_trees(jobs, workers=1, progress=None):
+def build_trees(jobs, workers=1, progress=None, job_progress=None):
     """tree_geometry(depth, r0, seed, **kw) for every (depth, r0, seed, kw) in
     jobs, in that order; with workers > 1 in forked worker processes (largest
     trees first), which must happen before the calling process touches a
-    GPU.  The result does not depend on the number of workers."""
+    GPU.  The result does not depend on the number of workers.  progress(msg)
+    is called after each tree; job_progress(msg), inside the job, as a tree
+    is built."""
+    global _JOB_PROGRESS
+    _JOB_PROGRESS = job_progress
     if workers <= 1 or len(jobs) <= 1:
         out = []
         for j in jobs:
@@ -118,7 +125,7 @@ def coupled_lambda(depth=6, r0=48.0, seed=MASTER_SEED + 4, arterial_sites=60e6):
 
 
 def coupled_pair(depth=6, r0=48.0, lam=None, vein_scale=1.5, seed=MASTER_SEED + 4, period=4000.0,
-                 tau=0.8, steps=20000, progress=None, workers=1):
+                 tau=0.8, steps=20000, progress=None, workers=1, job_progress=None):
     """Arterial tree (root velocity inlet, leaf pressure outlets) coupled 1:1
     at every leaf to the mirrored venous tree of the same seeded topology with
     radii scaled by vein_scale (leaf velocity inlets, root pressure outlet).
@@ -129,7 +136,7 @@ def coupled_pair(depth=6, r0=48.0, lam=None, vein_scale=1.5, seed=MASTER_SEED + 
         lam = 8.0
     art, ven = build_trees([(depth, r0, seed, dict(lam=lam)),
                             (depth, r0, seed, dict(lam=lam, radius_scale=vein_scale, mirror=True, venous=True))],
-                           workers=workers)
+                           workers=workers, job_progress=job_progress)
     if progress is not None:
         progress(f"arterial tree: {art.n} sites; venous tree: {ven.n} sites")
     inlet = pulsatile(rng, period=period)
