@@ -227,8 +227,9 @@ def choose_layout(hl, torch, geo, prec, layouts, autotune_ms, probe_steps, sched
             log(f"{prec} layout {order}: autotune kept {ctx.schedule()} of {n} candidates, "
                 f"median {b * 1e3:.1f} us/step (runner-up {r * 1e3:.1f}), spread {100 * sp:.1f} %")
         for drive in drives:
+            # warm-up long enough to capture and instantiate the graph (16 steps per replay)
             ctx.set_drive(drive)
-            ctx.step(4)
+            ctx.step(48)
             ms, _ = measure(ctx, torch, probe_steps)
             log(f"{prec} layout {order}: schedule {ctx.schedule()}, drive {DRIVES[drive]}, "
                 f"{geo.n * probe_steps / (ms * 1e-3) / 1e6:.0f} MLUPS")

@@ -52,6 +52,7 @@ struct hl_ctx {
     int32_t *d_emap = nullptr;
     std::vector<int64_t *> d_c2g;  // per domain: caller index -> internal index (device reads)
     float *d_bq = nullptr;
+    uint32_t *d_bq_off = nullptr;
     double *d_bphi = nullptr, *d_bnrm = nullptr;
     void *d_up[2] = {nullptr, nullptr};
     hl::Entry *d_entries = nullptr, *d_entries2 = nullptr;
@@ -119,7 +120,7 @@ void free_device(hl_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
     c->graph_steps = 0;
-    void *ps[] = {c->lat[0], c->lat[1], c->d_src, c->d_d16, c->d_bq, c->d_bphi, c->d_bnrm, c->d_up[0], c->d_up[1],
+    void *ps[] = {c->lat[0], c->lat[1], c->d_src, c->d_d16, c->d_bq, c->d_bq_off, c->d_bphi, c->d_bnrm, c->d_up[0], c->d_up[1],
                   c->d_entries, c->d_entries2, c->d_seg, c->d_io, c->d_pairs, c->d_ctrl, c->d_partials, c->d_stats,
                   c->d_bc, c->d_held, c->d_obs, c->d_fbuf};
     for (void *p : ps) dfree(p);
@@ -131,6 +132,7 @@ void free_device(hl_ctx *c) {
     c->d_src = nullptr;
     c->d_d16 = nullptr;
     c->d_bq = nullptr;
+    c->d_bq_off = nullptr;
     c->d_bphi = c->d_bnrm = nullptr;
     c->d_up[0] = c->d_up[1] = nullptr;
     c->d_entries = nullptr;
@@ -161,6 +163,7 @@ hl::KArgs make_args(hl_ctx *c) {
     a.src = c->d_src;
     a.d16 = c->d_d16;
     a.bq = c->d_bq;
+    a.bq_off = c->d_bq_off;
     a.bphi = c->d_bphi;
     a.up0 = c->d_up[0];
     a.up1 = c->d_up[1];
@@ -431,6 +434,7 @@ int commit(hl_ctx *c) {
     if ((rc = dalloc(c, &c->d_src, L.src.size())) != HL_OK) return rc;
     if (!L.d16.empty() && (rc = dalloc(c, &c->d_d16, L.d16.size())) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_bq, L.bq.size())) != HL_OK) return rc;
+    if ((rc = dalloc(c, &c->d_bq_off, L.bq_off.size())) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_bphi, L.bphi.size())) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_bnrm, L.bnrm.size())) != HL_OK) return rc;
     if ((rc = dalloc(c, &c->d_seg, c->L.hseg.size())) != HL_OK) return rc;
@@ -444,6 +448,7 @@ int commit(hl_ctx *c) {
     HIPC(c, hipMemcpy(c->d_src, L.src.data(), L.src.size() * 4, hipMemcpyHostToDevice));
     if (!L.d16.empty()) HIPC(c, hipMemcpy(c->d_d16, L.d16.data(), L.d16.size() * 2, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_bq, L.bq.data(), L.bq.size() * 4, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->d_bq_off, L.bq_off.data(), L.bq_off.size() * 4, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_bphi, L.bphi.data(), L.bphi.size() * 8, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_bnrm, L.bnrm.data(), L.bnrm.size() * 8, hipMemcpyHostToDevice));
     HIPC(c, hipMemcpy(c->d_seg, c->L.hseg.data(), c->L.hseg.size() * sizeof(hl::SegDev), hipMemcpyHostToDevice));
@@ -480,6 +485,7 @@ int commit(hl_ctx *c) {
     std::vector<int32_t>().swap(c->L.src);
     std::vector<int16_t>().swap(c->L.d16);
     std::vector<float>().swap(c->L.bq);
+    std::vector<uint32_t>().swap(c->L.bq_off);
     std::vector<double>().swap(c->L.bphi);
     std::vector<double>().swap(c->L.bnrm);
     c->committed = true;

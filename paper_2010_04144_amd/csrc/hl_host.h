@@ -82,7 +82,8 @@ struct Layout {
     std::vector<uint8_t> site_wall;  // interleaved layout: 1 where a site has a boundary link
     std::vector<int32_t> src;        // [18][N] pull table
     std::vector<int16_t> d16;        // [18][N] int16 pull deltas (empty when no site uses them)
-    std::vector<float> bq;           // [18][Nb] wall fractions
+    std::vector<float> bq;           // wall fractions of the wall links, boundary site by site, in direction order
+    std::vector<uint32_t> bq_off;    // [Nb + 1] first entry of each boundary site in bq
     std::vector<double> bphi, bnrm;  // [Nb], [3][Nb]
     std::vector<IoletDev> hio;
     std::vector<PairDev> hpairs;

@@ -11,7 +11,9 @@
 //              f*(t-1), or the raw f(t) right after a (re)initialisation.
 //   src        int32 [18][N] pull table: src[j-1][s] is the internal index of
 //              the site at x_s - c_j, or -1 (wall link) / -2-g (iolet g).
-//   bq         float [18][Nb] wall fraction q of the link (s, opp(j)).
+//   bq         float, the wall fractions q of the wall links (src = -1) of
+//              each boundary site b in direction order j = 1..18, starting at
+//              bq_off[b] (uint32 [Nb + 1]); q of the link (s, opp(j)).
 //   bphi       double [Nb] inlet profile factor max(0, 1 - r^2/R^2).
 //   bnrm       double [3][Nb] unit wall normal (0 for sites without walls).
 //   uprev[2]   [3][Nio] velocity of each iolet site at step t (parity t&1).
@@ -91,6 +93,7 @@ struct KArgs {
     const int32_t *src;
     const int16_t *d16;      // [18][N] upstream site minus s for K_NEAR / K_NEARWALL sites
     const float *bq;
+    const uint32_t *bq_off;
     const double *bphi;
     void *up0, *up1;
     const double *bnrm;

@@ -150,6 +150,28 @@ __device__ __forceinline__ size_t lidx(int i, int64_t s) {
     return ((((size_t)s >> TILE_SHIFT) * Q + (size_t)i) << TILE_SHIFT) | ((size_t)s & (TILE - 1));
 }
 
+// Wall fractions of site s (b = s - NB), one per direction j: q of the wall
+// link fed into j when sr[j] == -1 and the walls are Bouzidi walls, read from
+// the site's run of the compact list (its wall links in direction order),
+// else 1/2.  bz is uniform over the work-group.  The observation and moments
+// passes take this path for bulk sites too, where b may be negative: the
+// offset is read only for a site with a wall link, which the layout places at
+// or above NB.
+__device__ __forceinline__ void wall_fractions(const KArgs &a, int64_t b, bool bz, const int32_t (&sr)[Q],
+                                               float (&qv)[Q]) {
+    bool wall = false;
+#pragma unroll
+    for (int j = 1; j < Q; ++j) wall = wall || sr[j] == -1;
+    const float *qp = a.bq + ((bz && wall) ? a.bq_off[b] : 0u);
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < Q; ++j) {
+        const bool w = bz && sr[j] == -1;
+        qv[j] = w ? qp[k] : 0.5f;
+        k += w ? 1 : 0;
+    }
+}
+
 // Entry classes whose sites take the bulk path (every link fluid).
 __device__ __forceinline__ bool bulk_class(int klass) { return klass == K_BULK || klass == K_NEAR; }
 
@@ -287,8 +309,8 @@ __device__ __forceinline__ void gather(const KArgs &a, const Entry &e, const Seg
         // Bouzidi wall link, direction i itself (q >= 1/2)
         const bool need = (sr[ib] == -1) || (sr[ib] <= -2 && !outlet) || (bz && sr[i] == -1);
         own[i] = need ? ldc(lin + lidx(i, s), i) : R(0);
-        qv[i] = (bz && sr[i] == -1) ? a.bq[(size_t)(i - 1) * a.Nb + b] : 0.5f;
     }
+    wall_fractions(a, b, bz, sr, qv);
     // Phase 2: the boundary rules, from registers only.
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
@@ -838,8 +860,7 @@ __device__ __forceinline__ void aa_read(const KArgs &a, const Entry &e, const Se
     if (!BND) return;
     const bool bz = sg.wall_mode == WALL_BOUZIDI;
     const int64_t b = s - a.NB;
-#pragma unroll
-    for (int j = 1; j < Q; ++j) qv[j] = (bz && sr[j] == -1) ? a.bq[(size_t)(j - 1) * a.Nb + b] : 0.5f;
+    wall_fractions(a, b, bz, sr, qv);
     if (direct) return;
     // boundary rules of the stream t-1 -> t; x[j] holds f*_jb(s, t-1) (or a
     // final value) for every direction whose upstream voxel is not fluid.

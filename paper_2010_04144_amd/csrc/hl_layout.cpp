@@ -291,7 +291,7 @@ int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint
 
     // pull table, wall fractions, inlet profile, wall normals
     L.src.assign((size_t)18 * N, 0);
-    L.bq.assign((size_t)18 * std::max<int64_t>(Nb, 1), 0.5f);
+    std::vector<float> qfull((size_t)18 * std::max<int64_t>(Nb, 1), 0.5f);  // [18][Nb], compacted below
     L.bphi.assign(std::max<int64_t>(Nb, 1), 0.0);
     L.bnrm.assign((size_t)3 * std::max<int64_t>(Nb, 1), 0.0);
     L.hio.assign(io_count, IoletDev{});
@@ -314,7 +314,7 @@ int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint
         for (size_t e = 0; e < dm.q.size(); ++e) {
             const int64_t g = dm.c2g[dm.q_site[e]];
             const int j = opp_h(dm.q_dir[e]);
-            L.bq[(size_t)(j - 1) * Nb + (g - NB)] = dm.q[e];
+            qfull[(size_t)(j - 1) * Nb + (g - NB)] = dm.q[e];
         }
         std::vector<double> userw;
         std::vector<char> has_user;
@@ -382,6 +382,23 @@ int plan_layout(std::vector<Domain> &doms, const std::vector<PairH> &pairs, uint
             io.coupled = ih.coupled ? 1 : 0;
             io.seg = d;
         }
+    }
+    // wall fractions of the wall links only, boundary site by site
+    {
+        size_t nw = 0;
+        for (int64_t b = 0; b < Nb; ++b)
+            for (int j = 1; j < Q; ++j) nw += L.src[(size_t)(j - 1) * N + NB + b] == -1;
+        if (nw > (size_t)UINT32_MAX) return failf(err, HL_E_RANGE, "%zu wall links exceed the 32-bit offsets", nw);
+        L.bq.clear();
+        L.bq.reserve(std::max<size_t>(nw, 1));
+        L.bq_off.assign((size_t)Nb + 1, 0);
+        for (int64_t b = 0; b < Nb; ++b) {
+            L.bq_off[b] = (uint32_t)L.bq.size();
+            for (int j = 1; j < Q; ++j)
+                if (L.src[(size_t)(j - 1) * N + NB + b] == -1) L.bq.push_back(qfull[(size_t)(j - 1) * Nb + b]);
+        }
+        L.bq_off[Nb] = (uint32_t)L.bq.size();
+        if (L.bq.empty()) L.bq.push_back(0.5f);  // one element, never read
     }
     // coupling pairs grouped by arterial outlet, call order kept
     {
@@ -566,6 +583,41 @@ int check_layout(const std::vector<Domain> &doms, const Layout &L, int block, st
                     return failf(err, HL_E_RANGE, "pull index (%d, %lld) = %d is no site", j, (long long)g, v);
                 if (v <= -2 && -2 - v >= (int32_t)L.hio.size())
                     return failf(err, HL_E_RANGE, "pull index (%d, %lld) names iolet %d", j, (long long)g, -2 - v);
+            }
+        }
+    }
+    // wall fractions: one per wall link of each boundary site, the caller's q
+    // (or 1/2 where none was given) at the link's rank among the site's walls
+    if (L.bq_off.size() != (size_t)L.Nb + 1 || L.bq.empty() || L.bq_off[0] != 0)
+        return failf(err, HL_E_INVAL, "wall-fraction offsets hold %zu entries for %lld boundary sites", L.bq_off.size(),
+                     (long long)L.Nb);
+    for (int64_t b = 0; b < L.Nb; ++b) {
+        int64_t nwall = 0;
+        for (int j = 1; j < Q; ++j) nwall += L.src[(size_t)(j - 1) * N + L.NB + b] == -1;
+        if ((int64_t)L.bq_off[b + 1] - (int64_t)L.bq_off[b] != nwall)
+            return failf(err, HL_E_INVAL, "boundary site %lld has %lld wall links but %lld fractions", (long long)b,
+                         (long long)nwall, (long long)L.bq_off[b + 1] - (long long)L.bq_off[b]);
+    }
+    if ((size_t)L.bq_off[L.Nb] > L.bq.size()) return failf(err, HL_E_RANGE, "wall-fraction list too short");
+    for (int j = 1; j < Q; ++j)  // the kernels read a site's fractions only at or above NB
+        for (int64_t s = 0; s < L.NB; ++s)
+            if (L.src[(size_t)(j - 1) * N + s] == -1)
+                return failf(err, HL_E_INVAL, "site %lld below the boundary region has a wall link", (long long)s);
+    for (size_t d = 0; d < doms.size(); ++d) {
+        const Domain &dm = doms[d];
+        std::vector<float> given((size_t)18 * dm.n, -1.0f);
+        for (size_t e = 0; e < dm.q.size(); ++e) given[(size_t)(opp_h(dm.q_dir[e]) - 1) * dm.n + dm.q_site[e]] = dm.q[e];
+        for (int64_t x = 0; x < dm.n; ++x) {
+            const int64_t g = dm.c2g[x];
+            if (g < L.NB) continue;
+            uint32_t k = L.bq_off[g - L.NB];
+            for (int j = 1; j < Q; ++j) {
+                if (L.src[(size_t)(j - 1) * N + g] != -1) continue;
+                const float want = given[(size_t)(j - 1) * dm.n + x] >= 0.0f ? given[(size_t)(j - 1) * dm.n + x] : 0.5f;
+                if (L.bq[k] != want)
+                    return failf(err, HL_E_INVAL, "wall fraction (%d, %lld) of domain %zu is %g, not %g", j,
+                                 (long long)x, d, (double)L.bq[k], (double)want);
+                ++k;
             }
         }
     }
