@@ -318,18 +318,19 @@ def parity_developed(hl, ctx, geo, threads, t_dev, steps=3):
     return res
 
 
-def _compare(ctx, sysm):
+def _compare(ctx, sysm, dom=0):
     w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
-    rho_r, u_r = sysm.moments(0)
-    out = {"e_u": rel_err(ctx.velocity(0), u_r, u_r, 1e-4),
-           "e_rho": rel_err(ctx.density(0), rho_r, rho_r - 1.0, 1e-2)}
-    f_r = sysm.f(0)
-    out["e_f"] = rel_err(ctx.populations(0), f_r, f_r - w[:, None], 1e-3)
+    rho_r, u_r = sysm.moments(dom)
+    out = {"e_u": rel_err(ctx.velocity(dom), u_r, u_r, 1e-4),
+           "e_rho": rel_err(ctx.density(dom), rho_r, rho_r - 1.0, 1e-2)}
+    del rho_r, u_r
+    f_r = sysm.f(dom)
+    out["e_f"] = rel_err(ctx.populations(dom), f_r, f_r - w[:, None], 1e-3)
     del f_r
-    w_r = sysm.wss(0)
-    out["e_wss"] = rel_err(ctx.wss(0), w_r, w_r, 1e-6)
-    mu_r, mp_r, _ = sysm.iolet_stats(0)
-    mu, mp = ctx.iolet_stats(0)
+    w_r = sysm.wss(dom)
+    out["e_wss"] = rel_err(ctx.wss(dom), w_r, w_r, 1e-6)
+    mu_r, mp_r, _ = sysm.iolet_stats(dom)
+    mu, mp = ctx.iolet_stats(dom)
     out["e_iolet_u"] = rel_err(mu, mu_r, mu_r, 1e-4)
     out["e_iolet_p"] = rel_err(mp, mp_r, mp_r, 1e-2 / 3)
     out["tolerance"] = 1e-12
@@ -479,7 +480,60 @@ def run_coupled_full(hl, torch, args, wl):
                    "lattice_elements_19N": 19 * batched["sites"]},
         "batched": {"coupled_pair": batched},
     }
+    if args.coupled_parity > 0:
+        threads, _ = cpu_threads()
+        line["parity"] = {"developed": coupled_parity_developed(hl, torch, wl, args.coupled_parity, threads)}
     print(json.dumps(line), flush=True)
+
+
+def coupled_parity_developed(hl, torch, wl, t_dev, threads, steps=3, layout=40, schedule=(256, 11)):
+    """Parity of a coupled workload from a developed state: an FP64 context
+    of all its domains runs to step t_dev; its populations, its step counter
+    and the coupled values its last step used go into the oracle; both take
+    `steps` more steps and every output of every domain is compared."""
+    import oracle
+    t0 = time.perf_counter()
+    ctx = make_workload_ctx(hl, wl, "f64", torch, layout)
+    ctx.set_schedule(*schedule)
+    ctx.step(t_dev)
+    ctx.sync()
+    t = ctx.t
+    roots = [float(ctx.iolet_stats(d)[0][0]) for d in range(len(wl.domains))]
+    log(f"coupled parity: FP64 context at step {t} ({time.perf_counter() - t0:.1f} s), root mean velocities {roots}")
+    sysm = oracle.System(len(wl.domains))
+    for d, dm in enumerate(wl.domains):
+        sysm.set_geometry(d, dm.geo)
+        sysm.set_params(d, dm.tau, oracle.BOUZIDI if dm.bouzidi else oracle.SBB)
+        for k, io in enumerate(dm.geo.iolets):
+            if io.kind == "inlet" and k in dm.inlets:
+                a0, a, b, T = dm.inlets[k]
+                sysm.set_iolet(d, k, oracle.INLET, io.centre, io.normal, io.radius, a0, a, b, T)
+            if io.kind == "outlet" and k in dm.outlets:
+                r0, a, b, T = dm.outlets[k]
+                sysm.set_iolet(d, k, oracle.OUTLET, io.centre, io.normal, io.radius, r0, a, b, T)
+    for pr in wl.pairs:
+        sysm.couple(*pr)
+    sysm.set_coupling_mode(wl.mode)
+    sysm.init()
+    sysm.set_time(t)
+    for d in range(len(wl.domains)):
+        sysm.set_f(d, ctx.populations(d))
+        for k, v in enumerate(ctx.iolet_bc(d, which=1)):
+            sysm.set_held(d, k, v)
+    log(f"coupled parity: oracle loaded ({time.perf_counter() - t0:.1f} s)")
+    t1 = time.perf_counter()
+    sysm.step(steps, threads)
+    log(f"coupled parity: oracle {steps} steps in {time.perf_counter() - t1:.1f} s on {threads} threads")
+    ctx.step(steps)
+    res = {"from_step": t, "steps": steps, "root_mean_u": roots, "tolerance": 1e-12}
+    for d in range(len(wl.domains)):
+        res[f"domain {d}"] = _compare(ctx, sysm, d)
+        res[f"domain {d}"]["boundary_values"] = float(np.abs(ctx.iolet_bc(d, which=1) - sysm.last_bc(d)).max())
+    res["pass"] = all(res[f"domain {d}"]["pass"] for d in range(len(wl.domains)))
+    ctx.close()
+    del sysm
+    log(f"coupled parity: {json.dumps(res)}")
+    return res
 
 
 def _sched(text):
@@ -518,6 +572,8 @@ def main():
     ap.add_argument("--batched-drive", default="launch", choices=["launch", "graph"])
     ap.add_argument("--batched-precisions", default="f32,f64")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a 1 GiB device copy")
+    ap.add_argument("--coupled-parity", type=int, default=0,
+                    help="coupled-full: FP64 parity against the oracle from this step on (3 steps)")
     ap.add_argument("--coupled-steps", type=int, default=0,
                     help="coupled-full: run the FP32 context on to this many steps, logging the root means")
     ap.add_argument("--workload", default="artery", choices=["artery", "coupled-full"],

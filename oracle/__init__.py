@@ -56,6 +56,8 @@ def _load():
         "or_set_coupling_mode": (None, [_P, ct.c_int]),
         "or_init": (ct.c_int, [_P]),
         "or_set_f": (ct.c_int, [_P, ct.c_int, _D]),
+        "or_set_time": (ct.c_int, [_P, ct.c_int64]),
+        "or_set_held": (ct.c_int, [_P, ct.c_int, ct.c_int, ct.c_double]),
         "or_step": (ct.c_int, [_P, ct.c_int64, ct.c_int]),
         "or_time": (ct.c_int64, [_P]),
         "or_read_f": (ct.c_int, [_P, ct.c_int, _D]),
@@ -207,6 +209,14 @@ class System:
         f = _arr(f, np.float64)
         assert f.shape == (19, self.n[dom])
         self._chk(self._lib.or_set_f(self._h, dom, _d(f)), "set_f")
+
+    def set_time(self, t):
+        """Step counter of an injected state (waveform phase, exchange half)."""
+        self._chk(self._lib.or_set_time(self._h, int(t)), "set_time")
+
+    def set_held(self, dom, k, v):
+        """Held coupled value of iolet k of an injected state."""
+        self._chk(self._lib.or_set_held(self._h, dom, int(k), float(v)), "set_held")
 
     def step(self, nsteps, threads=1):
         self._chk(self._lib.or_step(self._h, int(nsteps), int(threads)), "step")

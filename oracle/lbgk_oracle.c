@@ -532,6 +532,22 @@ int or_set_f(or_sys *s, int dom, const double *f) {
     return 0;
 }
 
+/* State injection for comparisons from a state another run reached: the step
+ * counter (it selects the waveform phase and the forward/reverse half of the
+ * exchange) and the held coupled value of iolet k (the one a step that does
+ * not recompute it keeps).  Neither changes any arithmetic of the step. */
+int or_set_time(or_sys *s, int64_t t) {
+    if (t < 0) return -1;
+    s->t = t;
+    return 0;
+}
+
+int or_set_held(or_sys *s, int dom, int k, double v) {
+    if (dom < 0 || dom >= s->ndom || k < 0 || k >= s->d[dom].n_iolet) return -1;
+    s->d[dom].io[k].held = v;
+    return 0;
+}
+
 int or_step(or_sys *s, int64_t nsteps, int nthreads) {
     if (!s->ready) return -3;
     if (nthreads < 1) nthreads = 1;

@@ -569,6 +569,60 @@ def test_coupled_1to3_reaches_eq2_ratios(oracle_mod, mode):
     assert pb[:3].min() > 0
 
 
+def _coupled_1to3_pulsatile(oracle_mod, mode, steps):
+    """The 1:3 tubes with a pulsatile arterial inlet (the waveform phase then
+    depends on the step counter)."""
+    art = synth.tubes(1, radius=4.0, length=24)
+    ven = synth.tubes(3, radius=4.0, length=24)
+    dp = np.array([0.30, 0.52, 0.69])
+    s_fac = oracle_mod.velocity_factors(dp, [1.0, 0.6156, 0.5639], np.ones(3), 1.0)
+    sys_ = oracle_mod.System(2)
+    for d, g in enumerate((art, ven)):
+        sys_.set_geometry(d, g)
+        sys_.set_params(d, 0.8)
+    io = art.iolets[0]
+    sys_.set_iolet(0, 0, oracle_mod.INLET, io.centre, io.normal, io.radius, a0=0.01, a=(0.003,), b=(-0.002,),
+                   period=37.0)
+    for i in range(3):
+        sys_.couple(0, 1, 1, i, s_fac[i], dp[i])
+    sys_.set_coupling_mode(mode)
+    sys_.init()
+    sys_.step(steps)
+    return sys_
+
+
+@pytest.mark.parametrize("mode", ["alternate", "both"])
+def test_state_injection_resumes_bitwise(oracle_mod, mode):
+    """A run resumed from an injected state (populations, step counter, and
+    the held coupled values read back as the values the last step used)
+    continues bit for bit like the uninterrupted run.  The developed-state
+    comparisons with the GPU rely on this.  Odd and even resume steps, so
+    that either half of the alternating exchange comes first."""
+    m = oracle_mod.ALTERNATE if mode == "alternate" else oracle_mod.BOTH
+    for t0 in (211, 212):
+        full = _coupled_1to3_pulsatile(oracle_mod, m, t0 + 25)
+        part = _coupled_1to3_pulsatile(oracle_mod, m, t0)
+        fresh = _coupled_1to3_pulsatile(oracle_mod, m, 0)
+        fresh.set_time(t0)
+        for d in (0, 1):
+            fresh.set_f(d, part.f(d))
+            for k, v in enumerate(part.last_bc(d)):
+                fresh.set_held(d, k, v)
+        fresh.step(25)
+        assert fresh.t == full.t
+        for d in (0, 1):
+            assert np.array_equal(fresh.f(d), full.f(d))
+            assert np.array_equal(fresh.last_bc(d), full.last_bc(d))
+        # without the step counter the waveform phase and the exchange half differ
+        wrong = _coupled_1to3_pulsatile(oracle_mod, m, 0)
+        for d in (0, 1):
+            wrong.set_f(d, part.f(d))
+            for k, v in enumerate(part.last_bc(d)):
+                wrong.set_held(d, k, v)
+        wrong.step(25)
+        assert not np.array_equal(wrong.f(0), full.f(0))
+
+
 def test_velocity_reverse_reading_is_unstable(oracle_mod):
     """Sec. 3 leaves open what the reverse direction sets at an arterial
     outlet.  Read literally, as a velocity boundary whose mean is the mean over

@@ -227,6 +227,27 @@ def test_coupled_pair_twin(hl, oracle_mod, order):
         assert not bad, (d, bad, err)
 
 
+@pytest.mark.parametrize("t_dev", [800, 801])
+def test_coupled_pair_twin_from_developed_state(hl, oracle_mod, t_dev):
+    """The benchmark's developed-state parity of a coupled workload, on the
+    reduced twin: the FP64 GPU run reaches step t_dev (even and odd, so that
+    either half of the alternating exchange comes first), its populations,
+    step counter and the coupled values its last step used go into the
+    oracle, and three more steps agree to 1e-12 in both domains."""
+    import torch
+    import bench
+    wl = synth.workloads.coupled_pair(depth=3, r0=10.0, lam=6.0, period=300.0)
+    res = bench.coupled_parity_developed(hl, torch, wl, t_dev, THREADS)
+    print("coupled twin developed", res, flush=True)
+    assert res["from_step"] == t_dev
+    assert min(abs(u) for u in res["root_mean_u"]) > 1e-6   # flow has reached the venous root
+    for d in (0, 1):
+        err = {k: v for k, v in res[f"domain {d}"].items() if k.startswith("e_")}
+        assert max(err.values()) <= 1e-12, (d, err)
+        assert res[f"domain {d}"]["boundary_values"] <= 1e-13
+    assert res["pass"]
+
+
 def test_ensemble_twin(hl, oracle_mod):
     """Reduced twin of the ensemble: six trees of uneven size, each with its
     own tau and 3-harmonic inlet waveform, advanced in one context."""
