@@ -15,7 +15,9 @@
  *
  *   1. moments of f(n):  rho = sum_i f_i,  u = (sum_i c_i f_i + F(n)/2) / rho
  *   2. iolet means over the sites bordering each inlet/outlet (sites in the
- *      caller's order): mean u.n and mean rho, pressure c_s^2 (rho - rho0)
+ *      caller's order): mean u.n and mean (rho - rho0), pressure c_s^2 times
+ *      the latter (the deviations are summed, not the densities, so that the
+ *      leading rho0 of every term does not swamp a small mean)
  *   3. boundary values for step n: waveform series at t = n, or the coupled
  *      values (forward: venous inlet peak = s mean_u(arterial outlet) / phibar,
  *      phibar = mean inlet profile factor over the inlet's sites, so that the
@@ -117,7 +119,7 @@ typedef struct {
     double phibar;     /* mean profile factor over the bordering sites */
     /* means of the current f */
     int64_t area;
-    double mean_u, mean_rho;
+    double mean_u, mean_drho;  /* iolet means of u.n and of rho - rho0 */
 } iolet_t;
 
 typedef struct {
@@ -371,7 +373,7 @@ static void iolet_means(domain_t *d) {
             double un = 0.0;
             for (int a = 0; a < 3; ++a) un = un + d->u[(size_t)a * d->n + x] * d->io[k].nrm[a];
             su[k] = su[k] + un;
-            sr[k] = sr[k] + d->rho[x];
+            sr[k] = sr[k] + (d->rho[x] - RHO0);
             cnt[k] = cnt[k] + 1;
         }
     }
@@ -379,7 +381,7 @@ static void iolet_means(domain_t *d) {
         iolet_t *io = &d->io[k];
         io->area = cnt[k];
         io->mean_u = cnt[k] ? su[k] / (double)cnt[k] : 0.0;
-        io->mean_rho = cnt[k] ? sr[k] / (double)cnt[k] : RHO0;
+        io->mean_drho = cnt[k] ? sr[k] / (double)cnt[k] : 0.0;
     }
     free(su); free(sr); free(cnt);
 }
@@ -413,7 +415,7 @@ static void boundary_values(or_sys *s) {
                     /* the vein carries s times the artery's mean velocity */
                     sum = sum + s->d[o->db].io[o->kb].mean_u / o->s;
                 } else {
-                    double pv = (s->d[o->db].io[o->kb].mean_rho - RHO0) / 3.0;
+                    double pv = s->d[o->db].io[o->kb].mean_drho / 3.0;
                     sum = sum + pv / (1.0 - o->delta);
                 }
                 cnt = cnt + 1;
@@ -602,7 +604,7 @@ int or_read_iolet_stats(or_sys *s, int dom, double *mean_u, double *mean_p, int6
     domain_t *d = &s->d[dom];
     for (int k = 0; k < d->n_iolet; ++k) {
         mean_u[k] = d->io[k].mean_u;
-        mean_p[k] = (d->io[k].mean_rho - RHO0) / 3.0;
+        mean_p[k] = d->io[k].mean_drho / 3.0;
         area[k] = d->io[k].area;
     }
     return 0;

@@ -892,7 +892,7 @@ int hl_read_iolet_stats(hl_ctx *ctx, int32_t dom, double *mean_u, double *mean_p
     HIPC(ctx, hipMemcpy(st.data(), ctx->d_stats, st.size() * 8, hipMemcpyDeviceToHost));
     for (int k = 0; k < d.n_iolet; ++k) {
         mean_u[k] = st[d.io_base + k];
-        mean_p[k] = (st[nio + d.io_base + k] - hl::RHO0) / 3.0;
+        mean_p[k] = st[nio + d.io_base + k] / 3.0;  // the device holds the mean of rho - rho0
     }
     return read_nan(ctx);
 }

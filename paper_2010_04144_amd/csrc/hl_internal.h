@@ -114,7 +114,7 @@ struct KArgs {
     int32_t n_emap;          // emap[b] (nothing when < 0); n_emap work-groups (null: storage order)
     Ctrl *ctrl;
     double *partials;  // [2][n_entries]
-    double *stats;     // [2][n_io]: mean u.n, mean rho
+    double *stats;     // [2][n_io]: mean u.n, mean rho - rho0
     double *bc;        // [2][n_io] boundary values by step parity
     double *held;      // [n_io] held coupled values
     double *obs;       // [5][obs_stride] rho, ux, uy, uz, wss of the sites in [obs_lo, obs_hi)

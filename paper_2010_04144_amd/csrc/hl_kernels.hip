@@ -433,7 +433,7 @@ __global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
                 continue;
             }
             mu[k] = io.area > 0.0 ? su / io.area : 0.0;
-            mr[k] = io.area > 0.0 ? sr / io.area : RHO0;
+            mr[k] = io.area > 0.0 ? sr / io.area : 0.0;  // mean of rho - rho0
             if (!isfinite(su) || !isfinite(sr)) a.ctrl->nan_flag = 1;
             if (!io.coupled) a.bc[(tn & 1) * a.n_io + k] = series_at(io, tn);
         }
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(256) k_finalize(KArgs a, int mode) {
                 } else {
                     for (int p = io.pair_lo; p < io.pair_lo + io.pair_n; ++p) {
                         const PairDev pr = a.pairs[p];
-                        const double pv = (mr[pr.in_g] - RHO0) / 3.0;
+                        const double pv = mr[pr.in_g] / 3.0;
                         sum = sum + pv / (1.0 - pr.delta);
                     }
                     a.held[k] = RHO0 + 3.0 * (sum / (double)io.pair_n);
@@ -652,10 +652,10 @@ __device__ __forceinline__ void step_body(const KArgs &a) {
 
     if (klass == K_IOLET) {
         const IoletDev &io = a.io[tag_iolet(e.tag)];
-        double un = 0.0, rh = 0.0;
+        double un = 0.0, rh = 0.0;  // u.n and rho - rho0 (summed as deviations: no cancellation)
         if (act) {
             un = (double)ux * io.nrm[0] + (double)uy * io.nrm[1] + (double)uz * io.nrm[2];
-            rh = (double)rho;
+            rh = OFF ? (double)drho : (double)rho - RHO0;
         }
         const double su = block_sum(un, lds);
         const double sr = block_sum(rh, lds);
@@ -923,7 +923,7 @@ __device__ __forceinline__ void aa_moments(const KArgs &a, const Entry &e, int e
     using R = typename Arith<T>::R;
     constexpr bool OFF = Arith<T>::OFF;
     const int klass = tag_class(e.tag);
-    R rho = 1, ux = 0, uy = 0, uz = 0;
+    R rho = 1, drho = 0, ux = 0, uy = 0, uz = 0;
     bool bad = false;
     if (act) {
         R m0 = 0, jx = 0, jy = 0, jz = 0;
@@ -935,6 +935,7 @@ __device__ __forceinline__ void aa_moments(const KArgs &a, const Entry &e, int e
             if (CZ[i]) jz += R(CZ[i]) * x[i];
         }
         rho = OFF ? R(RHO0) + m0 : m0;
+        drho = OFF ? m0 : m0 - R(RHO0);
         ux = over(jx + R(0.5) * Fx, rho);
         uy = over(jy + R(0.5) * Fy, rho);
         uz = over(jz + R(0.5) * Fz, rho);
@@ -950,10 +951,10 @@ __device__ __forceinline__ void aa_moments(const KArgs &a, const Entry &e, int e
     if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) a.ctrl->nan_flag = 1;
     if (klass == K_IOLET) {
         const IoletDev &io = a.io[tag_iolet(e.tag)];
-        double un = 0.0, rh = 0.0;
+        double un = 0.0, rh = 0.0;  // u.n and rho - rho0 (summed as deviations: no cancellation)
         if (act) {
             un = (double)ux * io.nrm[0] + (double)uy * io.nrm[1] + (double)uz * io.nrm[2];
-            rh = (double)rho;
+            rh = OFF ? (double)drho : (double)rho - RHO0;
         }
         const double su = block_sum(un, lds);
         const double sr = block_sum(rh, lds);

@@ -76,9 +76,9 @@ MUTANTS = [
      "d->fn[(size_t)ib * n + x] = feq[i];",
      ["test_open_domain_mass_budget"]),
     ("iolet mean density: wrong count",
-     "io->mean_rho = cnt[k] ? sr[k] / (double)cnt[k] : RHO0;",
-     "io->mean_rho = cnt[k] ? sr[k] / (double)(cnt[k] + 1) : RHO0;",
-     ["test_hagen_poiseuille_cylinder"]),
+     "io->mean_drho = cnt[k] ? sr[k] / (double)cnt[k] : 0.0;",
+     "io->mean_drho = cnt[k] ? sr[k] / (double)(cnt[k] + 1) : 0.0;",
+     ["test_iolet_means_are_site_averages"]),
     ("wall shear stress: viscous prefactor",
      "double pref = -(1.0 - 1.0 / (2.0 * d->tau));",
      "double pref = -(1.0 - 1.0 / d->tau);",

@@ -7,6 +7,7 @@ Each test is chosen so that a plausible slip in the oracle (a dropped term,
 a wrong sign or index, a swapped branch) makes it fail.
 """
 import itertools
+import math
 import json
 import os
 
@@ -187,6 +188,29 @@ def test_open_domain_mass_budget(oracle_mod):
     budget = _neumaier(terms)
     assert abs(budget) > 1e-4                      # the iolets do move mass
     assert abs((m1 - m0) - budget) < 1e-13 * n
+
+
+def test_iolet_means_are_site_averages(oracle_mod):
+    """The iolet means that feed the exchange and the readout are plain
+    averages over the sites bordering each iolet: mean u.n with the iolet's
+    unit normal and mean gauge pressure (rho - rho0)/3, recomputed here from
+    the oracle's per-site moments and the geometry's neighbour codes."""
+    geo = synth.cylinder(nz=16)
+    s = _system(oracle_mod, geo, tau=0.7, u_in=0.02, rho_out=1.002)
+    s.step(40)
+    rho, u = s.moments()
+    mu, mp, area = s.iolet_stats()
+    codes = geo.nbr[1:]
+    for k, io in enumerate(geo.iolets):
+        sites = np.flatnonzero((codes == -2 - k).any(axis=0))
+        assert area[k] == sites.size > 0
+        nrm = np.asarray(io.normal, float)
+        nrm = nrm / np.linalg.norm(nrm)
+        want_u = math.fsum((nrm @ u[:, sites]).tolist()) / sites.size
+        want_p = math.fsum(((rho[sites] - 1.0) / 3.0).tolist()) / sites.size
+        assert abs(mu[k] - want_u) < 1e-15, (k, mu[k], want_u)
+        assert abs(mp[k] - want_p) < 1e-15, (k, mp[k], want_p)
+    assert abs(mp[1]) > 1e-4 and abs(mu[0]) > 1e-3   # the outlet pressure and inlet flow are not trivial
 
 
 def _dense_reference(solid, F, tau, steps):
