@@ -495,8 +495,11 @@ def coupled_parity_developed(hl, torch, wl, t_dev, threads, steps=3, layout=40, 
     t0 = time.perf_counter()
     ctx = make_workload_ctx(hl, wl, "f64", torch, layout)
     ctx.set_schedule(*schedule)
-    ctx.step(t_dev)
-    ctx.sync()
+    chunk = 2000
+    while ctx.t < t_dev:
+        ctx.step(min(chunk, t_dev - ctx.t))
+        ctx.sync()
+        log(f"coupled parity: FP64 context at step {ctx.t}")
     t = ctx.t
     roots = [float(ctx.iolet_stats(d)[0][0]) for d in range(len(wl.domains))]
     log(f"coupled parity: FP64 context at step {t} ({time.perf_counter() - t0:.1f} s), root mean velocities {roots}")
@@ -522,8 +525,9 @@ def coupled_parity_developed(hl, torch, wl, t_dev, threads, steps=3, layout=40, 
             sysm.set_held(d, k, v)
     log(f"coupled parity: oracle loaded ({time.perf_counter() - t0:.1f} s)")
     t1 = time.perf_counter()
-    sysm.step(steps, threads)
-    log(f"coupled parity: oracle {steps} steps in {time.perf_counter() - t1:.1f} s on {threads} threads")
+    for k in range(steps):
+        sysm.step(1, threads)
+        log(f"coupled parity: oracle step {k + 1} of {steps} done ({time.perf_counter() - t1:.1f} s on {threads} threads)")
     ctx.step(steps)
     res = {"from_step": t, "steps": steps, "root_mean_u": roots, "tolerance": 1e-12}
     for d in range(len(wl.domains)):
