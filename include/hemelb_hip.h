@@ -406,8 +406,9 @@ int hl_get_info(hl_ctx *ctx, hl_info *out);
  * events recorded on the context stream around each kernel; return the mean
  * duration in milliseconds of the bulk-site kernel and of the boundary-site
  * kernel of one step (with HL_SCHED_FUSED: 0 and the fused kernel).  The
- * one-work-group finalize kernel is not included.  The steps are real steps
- * (t advances). */
+ * one-work-group finalize kernel (queued every step only when domains are
+ * coupled) and the step-counter update after the steps are not included.  The
+ * steps are real steps (t advances). */
 int hl_time_kernels(hl_ctx *ctx, int64_t nsteps, double *ms_bulk, double *ms_bnd);
 
 /* ---- coupling construction (host only, no context or device) ------------- */
