@@ -233,6 +233,53 @@ def test_graph_and_launch_drivers_are_bitwise_equal(hl):
     assert np.array_equal(res[0], res[1])
 
 
+@pytest.mark.parametrize("order,spg", [(0, 7), (16, 8)])
+def test_time_dependent_graph_replay(hl, oracle_mod, order, spg):
+    """Time-dependent boundaries and force under graph replay: each launch of a
+    captured batch works on its own step (the inlet and outlet series, the
+    body force and, in the coupled case, the exchange parity all follow it),
+    so replays equal plain launches bit for bit and match the oracle.  Two
+    lattices and in place; a batch that is not a whole number of graphs."""
+    geo = synth.tubes(2, radius=4.0, length=20)
+    sc = Scenario([Dom(geo, tau=0.7, F0=(0.0, 1e-6, 2e-6), omega=0.05,
+                       inlets={0: (0.008, (0.002, -0.001), (0.001, 0.0), 23.0), 1: (0.004, (0.001,), (0.0,), 17.0)},
+                       outlets={2: (1.0, (0.0005,), (0.0002,), 29.0), 3: (1.001, (), (), 1.0)})])
+    res = []
+    for drive, n in ((hl.HL_DRIVE_LAUNCH, 1), (hl.HL_DRIVE_GRAPH, spg)):
+        g = build_gpu(sc, hl, "f64", order=order)
+        g.set_drive(drive, n)
+        g.step(3)
+        g.step(5 * spg + 3)
+        res.append((g.populations(0), g.iolet_bc(0, which=1), g))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    o = build_oracle(sc, oracle_mod)
+    o.step(5 * spg + 6)
+    check64(errors(res[1][2], o))
+    np.testing.assert_allclose(res[1][1], o.last_bc(0), rtol=1e-13, atol=1e-15)
+
+
+def test_coupled_graph_replay(hl, oracle_mod):
+    """The coupled exchange under graph replay (the finalize kernel of every
+    step takes its step's parity from the launch offset): replays equal plain
+    launches bit for bit in both exchange modes."""
+    art = synth.tubes(1, radius=4.0, length=24)
+    ven = synth.tubes(3, radius=4.0, length=24)
+    for mode in (0, hl.HL_BOTH_EACH_STEP):
+        res = []
+        for drive, n in ((hl.HL_DRIVE_LAUNCH, 1), (hl.HL_DRIVE_GRAPH, 6)):
+            sc = Scenario([Dom(art, tau=0.8, inlets={0: (0.01, (0.002,), (0.0,), 40.0)}),
+                           Dom(ven, tau=0.8, outlets={k: (1.0, (), (), 1.0) for k in range(3, 6)})],
+                          pairs=[(0, 1, 1, i, 0.3 + 0.1 * i, 0.3 + 0.2 * i) for i in range(3)], mode=mode)
+            g = build_gpu(sc, hl, "f64")
+            g.set_drive(drive, n)
+            g.step(1)
+            g.step(37)
+            res.append([g.populations(d) for d in (0, 1)] + [g.iolet_bc(d, which=1) for d in (0, 1)])
+        for a, b in zip(res[0], res[1]):
+            assert np.array_equal(a, b)
+
+
 def test_checkpoint_resume_bitwise(hl):
     for prec in ("f64", "f32", "f16", "f16w", "f16sr"):
         a = build_gpu(cylinder_scenario(nz=16), hl, prec)
