@@ -151,9 +151,16 @@ def cpu_quota():
     return None
 
 
-def rel_err(a, b, scale, floor=0.0):
-    s = max(float(np.max(np.abs(scale))) if np.size(scale) else 0.0, floor)
-    return float(np.max(np.abs(a - b)) / s) if s > 0 else float(np.max(np.abs(a - b)))
+def rel_err(a, b, scale, floor=0.0, record=None, name=None):
+    """max |a - b| over the largest |scale|, or `floor` when that is smaller;
+    with `record`, also stores the absolute difference and the signal size
+    under `name`."""
+    sig = float(np.max(np.abs(scale))) if np.size(scale) else 0.0
+    s = max(sig, floor)
+    d = float(np.max(np.abs(a - b))) if np.size(a) else 0.0
+    if record is not None:
+        record[name] = {"abs": d, "signal": sig, "floor": floor}
+    return d / s if s > 0 else d
 
 
 # --------------------------------------------------------------------------
@@ -320,19 +327,21 @@ def parity_developed(hl, ctx, geo, threads, t_dev, steps=3):
 
 def _compare(ctx, sysm, dom=0):
     w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    detail = {}
     rho_r, u_r = sysm.moments(dom)
-    out = {"e_u": rel_err(ctx.velocity(dom), u_r, u_r, 1e-4),
-           "e_rho": rel_err(ctx.density(dom), rho_r, rho_r - 1.0, 1e-2)}
+    out = {"e_u": rel_err(ctx.velocity(dom), u_r, u_r, 1e-4, detail, "u"),
+           "e_rho": rel_err(ctx.density(dom), rho_r, rho_r - 1.0, 1e-2, detail, "rho")}
     del rho_r, u_r
     f_r = sysm.f(dom)
-    out["e_f"] = rel_err(ctx.populations(dom), f_r, f_r - w[:, None], 1e-3)
+    out["e_f"] = rel_err(ctx.populations(dom), f_r, f_r - w[:, None], 1e-3, detail, "f")
     del f_r
     w_r = sysm.wss(dom)
-    out["e_wss"] = rel_err(ctx.wss(dom), w_r, w_r, 1e-6)
+    out["e_wss"] = rel_err(ctx.wss(dom), w_r, w_r, 1e-6, detail, "wss")
     mu_r, mp_r, _ = sysm.iolet_stats(dom)
     mu, mp = ctx.iolet_stats(dom)
-    out["e_iolet_u"] = rel_err(mu, mu_r, mu_r, 1e-4)
-    out["e_iolet_p"] = rel_err(mp, mp_r, mp_r, 1e-2 / 3)
+    out["e_iolet_u"] = rel_err(mu, mu_r, mu_r, 1e-4, detail, "iolet_u")
+    out["e_iolet_p"] = rel_err(mp, mp_r, mp_r, 1e-2 / 3, detail, "iolet_p")
+    out["detail"] = detail
     out["tolerance"] = 1e-12
     out["pass"] = all(v <= 1e-12 for k, v in out.items() if k.startswith("e_"))
     return out
