@@ -75,6 +75,10 @@ MUTANTS = [
      "d->fn[(size_t)ib * n + x] = feq[ib];",
      "d->fn[(size_t)ib * n + x] = feq[i];",
      ["test_open_domain_mass_budget"]),
+    ("iolet mean pressure: the density summed instead of its deviation",
+     "sr[k] = sr[k] + (d->rho[x] - RHO0);",
+     "sr[k] = sr[k] + d->rho[x];",
+     ["test_iolet_means_are_site_averages"]),
     ("iolet mean density: wrong count",
      "io->mean_drho = cnt[k] ? sr[k] / (double)cnt[k] : 0.0;",
      "io->mean_drho = cnt[k] ? sr[k] / (double)(cnt[k] + 1) : 0.0;",
