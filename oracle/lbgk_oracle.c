@@ -48,9 +48,12 @@
  *          rule above with the outlet's outward normal
  *   6. swap the two arrays.
  *
- * Parity unpinned: the reverse half of the coupling in step 3 is a reading
- * of Sec. 3 that no printed number fixes; the tests check only what follows
- * from it (flux conservation, settling to the Eq. (2) ratios).
+ * The reverse half of the coupling in step 3 is a reading of Sec. 3 that no
+ * printed number fixes; the tests pin what follows from it (flux
+ * conservation, settling to the Eq. (2) ratios, and the steady pressure drop
+ * of two coupled tubes scaling with 1/(1 - dP/P0) as Eq. (1) requires).
+ * Parity unpinned: the velocity-reverse mode (VEL), held only to its rest
+ * state and its instability.
  *
  * Sums run over directions in index order and over sites in caller order.
  * Build with -ffp-contract=off so every product and sum is rounded as written.

@@ -94,7 +94,7 @@ MUTANTS = [
     ("coupling reverse rule: Eq. (1) solved with the wrong sign",
      "sum = sum + pv / (1.0 - o->delta);",
      "sum = sum + pv / (1.0 + o->delta);",
-     ["test_coupled_1to3_reaches_eq2_ratios"]),
+     ["test_coupled_1to3_reaches_eq2_ratios", "test_reverse_rule_sets_the_pressure_drop"]),
 ]
 
 

@@ -593,6 +593,44 @@ def test_coupled_1to3_reaches_eq2_ratios(oracle_mod, mode):
     assert pb[:3].min() > 0
 
 
+def _coupled_halves(oracle_mod, delta, steps=3000):
+    """Two equal tubes coupled 1:1 (s = 1): the arterial one driven at its
+    inlet, the venous one open at its outlet at rho0.  Returns the arterial
+    inlet mean pressure and the mean velocities at the coupled pair."""
+    art = synth.tubes(1, radius=4.0, length=24)
+    ven = synth.tubes(1, radius=4.0, length=24)
+    s = oracle_mod.System(2)
+    for d, g in enumerate((art, ven)):
+        s.set_geometry(d, g)
+        s.set_params(d, 0.8)
+    io = art.iolets[0]
+    s.set_iolet(0, 0, oracle_mod.INLET, io.centre, io.normal, io.radius, a0=0.01)
+    io = ven.iolets[1]
+    s.set_iolet(1, 1, oracle_mod.OUTLET, io.centre, io.normal, io.radius, a0=1.0)
+    s.couple(0, 1, 1, 0, 1.0, delta)
+    s.set_coupling_mode(oracle_mod.ALTERNATE)
+    s.init()
+    s.step(steps)
+    ua, pa, _ = s.iolet_stats(0)
+    uv, _, _ = s.iolet_stats(1)
+    return pa[0], ua[1], uv[0]
+
+
+def test_reverse_rule_sets_the_pressure_drop(oracle_mod):
+    """Eq. (1) at system level: with the flux fixed by the arterial inlet, the
+    two tubes carry the same Poiseuille pressure drop, so the steady inlet
+    pressure is drop + p_outlet = drop (1 + 1/(1 - dP/P0)) when the arterial
+    outlet pressure is the venous inlet pressure over (1 - dP/P0).  The ratio
+    of the inlet pressures at dP/P0 = 0.6 and at dP/P0 -> 0 must therefore be
+    (1 + 1/0.4)/2 = 1.75 (measured 1.716: the two halves' entrance and exit
+    regions differ slightly); a rule that divided by (1 + dP/P0) would give
+    0.81."""
+    p0, _, _ = _coupled_halves(oracle_mod, 1e-9)
+    p6, _, _ = _coupled_halves(oracle_mod, 0.6)
+    assert p0 > 0
+    assert abs(p6 / p0 - 1.75) < 0.03 * 1.75, p6 / p0
+
+
 def _coupled_1to3_pulsatile(oracle_mod, mode, steps):
     """The 1:3 tubes with a pulsatile arterial inlet (the waveform phase then
     depends on the step counter)."""
