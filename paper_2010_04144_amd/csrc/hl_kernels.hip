@@ -1298,7 +1298,8 @@ __global__ void __launch_bounds__(256) k_aa_load_odd(KArgs a) {
 // launchers
 // ---------------------------------------------------------------------------
 // part: 0 = every launch of the step, 1 = the bulk-site kernel, 2 = the
-// boundary-site (or fused) kernel, 3 = the finalize kernel.
+// boundary-site (or fused) kernel, 3 = the finalize kernel (launched only
+// when domains are coupled).
 template <typename T>
 static int step_t(const KArgs &a0, int n_bulk, int n_bnd, int block, hipStream_t st, int part, bool fused) {
     KArgs a = a0;
