@@ -61,3 +61,19 @@ def test_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_relative_error_and_its_record(bench):
+    """The parity metric: the largest deviation over the largest signal, or
+    over the floor when the signal is smaller; the record keeps the absolute
+    deviation and the signal size, so a ratio held up by the floor shows."""
+    import numpy as np
+    a = np.array([1.0, 2.0, 3.0])
+    b = np.array([1.0, 2.5, 3.0])
+    rec = {}
+    assert bench.rel_err(a, b, b, 0.0, rec, "x") == pytest.approx(0.5 / 3.0)
+    assert rec["x"] == {"abs": 0.5, "signal": 3.0, "floor": 0.0}
+    small = np.array([1e-9, -2e-9])
+    assert bench.rel_err(small, small + 1e-18, small, 1e-4, rec, "y") == pytest.approx(1e-14)
+    assert rec["y"]["signal"] == pytest.approx(2e-9) and rec["y"]["floor"] == 1e-4
+    assert bench.rel_err(np.zeros(2), np.full(2, 3e-17), np.zeros(2)) == pytest.approx(3e-17)
