@@ -59,6 +59,12 @@ def test_layout_planner_under_sanitizers():
         "coupled": [synth.tubes(1, radius=4.0, length=12), synth.tubes(3, radius=4.0, length=12)],
         "tree_pair": [synth.tree_geometry(2, 6.0, 7, lam=6.0),
                       synth.tree_geometry(2, 6.0, 7, lam=6.0, radius_scale=1.5, mirror=True, venous=True)],
+        # random porous blocks: isolated sites, one-voxel channels, sites walled on most links,
+        # bricks that are nearly empty; closed and periodic in x
+        "porous": [synth.box(21, 19, 23, periodic=(False, False, False),
+                             solid=np.random.default_rng(5).random((23, 19, 21)) < 0.35).with_q("random", seed=6),
+                   synth.box(34, 9, 11, periodic=(True, False, False),
+                             solid=np.random.default_rng(8).random((11, 9, 34)) < 0.25).with_q("random", seed=9)],
     }
     with tempfile.TemporaryDirectory() as tmp:
         exe = os.path.join(tmp, "layout_check")
