@@ -95,6 +95,66 @@ MUTANTS = [
      "sum = sum + pv / (1.0 - o->delta);",
      "sum = sum + pv / (1.0 + o->delta);",
      ["test_coupled_1to3_reaches_eq2_ratios", "test_reverse_rule_sets_the_pressure_drop"]),
+    ("coupling reverse rule: venous pressures summed, not averaged",
+     "out->held = RHO0 + 3.0 * (sum / (double)cnt);",
+     "out->held = RHO0 + 3.0 * sum;",
+     ["test_coupled_1to3_reaches_eq2_ratios"]),
+    ("coupling reverse rule: pressure not converted to density",
+     "out->held = RHO0 + 3.0 * (sum / (double)cnt);",
+     "out->held = RHO0 + (sum / (double)cnt);",
+     ["test_coupled_1to3_reaches_eq2_ratios", "test_reverse_rule_sets_the_pressure_drop"]),
+    ("coupling forward rule: velocity factor dropped",
+     "in->held = in->phibar > 0.0 ? pr->s * s->d[pr->da].io[pr->ka].mean_u / in->phibar : 0.0;",
+     "in->held = in->phibar > 0.0 ? s->d[pr->da].io[pr->ka].mean_u / in->phibar : 0.0;",
+     ["test_coupled_1to3_reaches_eq2_ratios"]),
+    ("coupling forward rule: mean velocity used as the profile peak",
+     "in->held = in->phibar > 0.0 ? pr->s * s->d[pr->da].io[pr->ka].mean_u / in->phibar : 0.0;",
+     "in->held = in->phibar > 0.0 ? pr->s * s->d[pr->da].io[pr->ka].mean_u : 0.0;",
+     ["test_coupled_1to3_reaches_eq2_ratios"]),
+    ("coupling: both directions exchanged on the same step parity",
+     "int rev = (s->mode & COUPLE_BOTH) || (s->t % 2 == 1);",
+     "int rev = (s->mode & COUPLE_BOTH) || (s->t % 2 == 0);",
+     ["test_exchange_directions_per_step"]),
+    ("body force: sine for cosine",
+     "double c = cos(d->omega * (double)t);",
+     "double c = sin(d->omega * (double)t);",
+     ["test_time_dependent_force_momentum_budget", "test_womersley_pipe"]),
+    ("body force: taken one step late",
+     "double c = cos(d->omega * (double)t);",
+     "double c = cos(d->omega * (double)(t + 1));",
+     ["test_time_dependent_force_momentum_budget"]),
+    ("collision: relaxation rate tau for 1/tau",
+     "fstar[i] = f[i] - (f[i] - feq[i]) / tau + pref * W[i] * s;",
+     "fstar[i] = f[i] - (f[i] - feq[i]) * tau + pref * W[i] * s;",
+     ["test_collision_conserves_and_relaxes"]),
+    ("Guo source: prefactor 1 - 1/tau",
+     "double pref = 1.0 - 1.0 / (2.0 * tau);",
+     "double pref = 1.0 - 1.0 / tau;",
+     ["test_collision_conserves_and_relaxes", "test_time_dependent_force_momentum_budget"]),
+    ("inlet: Ladd factor halved",
+     "d->fn[(size_t)ib * n + x] = fsi - 6.0 * W[i] * RHO0 * cu;",
+     "d->fn[(size_t)ib * n + x] = fsi - 3.0 * W[i] * RHO0 * cu;",
+     ["test_open_domain_mass_budget", "test_hagen_poiseuille_cylinder"]),
+    ("inlet profile: distance along the normal kept",
+     "double r2 = dd - dn * dn;",
+     "double r2 = dd;",
+     ["test_open_domain_mass_budget"]),
+    ("outlet: equilibrium at rest instead of at the site's velocity",
+     "for (int a = 0; a < 3; ++a) u[a] = d->u[(size_t)a * n + x];\n                    or_feq(io->bc, u, feq);",
+     "for (int a = 0; a < 3; ++a) u[a] = 0.0;\n                    or_feq(io->bc, u, feq);",
+     ["test_open_domain_mass_budget", "test_hagen_poiseuille_cylinder"]),
+    ("series: evaluated one step ahead",
+     "io->bc = io->coupled ? io->held : series_at(&io->wave, (double)s->t);",
+     "io->bc = io->coupled ? io->held : series_at(&io->wave, (double)(s->t + 1));",
+     ["test_waveform_series_period_mean_and_harmonics"]),
+    ("wall shear stress: normal traction kept",
+     "double sx = tr[0] - tn * nv[0], sy = tr[1] - tn * nv[1], sz = tr[2] - tn * nv[2];",
+     "double sx = tr[0] + 0.0 * tn, sy = tr[1], sz = tr[2];",
+     ["test_wall_shear_stress_is_the_tangential_traction"]),
+    ("Eq. (2): area factor dropped",
+     "v[i] = (A0 / A[i]) * ratio / sum;",
+     "v[i] = ratio / sum;",
+     ["test_velocity_factors_conserve_mass"]),
 ]
 
 

@@ -324,6 +324,35 @@ def test_wall_shear_stress_plane_poiseuille(oracle_mod):
     assert np.abs(wss[edge] - F * (H - 1) / 2).max() / (F * (H - 1) / 2) < 1e-6
 
 
+def test_wall_shear_stress_is_the_tangential_traction(oracle_mod):
+    """A state whose non-equilibrium second moment is a chosen symmetric Pi
+    (f = feq + (9/2) w_i (c_i c_i - I/3) : Pi adds no mass or momentum and has
+    exactly that second moment) at the walls of a flat channel, normal +-y:
+    the viscous stress is -(1 - 1/(2 tau)) Pi, so the wall shear stress is
+    (1 - 1/(2 tau)) sqrt(Pi_xy^2 + Pi_zy^2) whatever the normal stresses
+    Pi_xx, Pi_yy, Pi_zz and the in-plane Pi_xz are."""
+    c, w = oracle_mod.lattice()
+    geo = synth.channel(nx=2, ny=4, nz=2)
+    tau = 0.7
+    s = _system(oracle_mod, geo, tau=tau)
+    Pi = np.array([[3e-4, 2e-4, -5e-4],
+                   [2e-4, 7e-4, -1.5e-4],
+                   [-5e-4, -1.5e-4, -4e-4]])
+    Qc = np.einsum("ia,ib->iab", c, c) - np.eye(3)[None] / 3.0
+    fneq = 4.5 * w * np.einsum("iab,ab->i", Qc, Pi)
+    assert abs(fneq.sum()) < 1e-18 and np.abs(c.T @ fneq).max() < 1e-18
+    assert np.abs(np.einsum("ia,ib,i->ab", c, c, fneq) - Pi).max() < 1e-18
+    feq = oracle_mod.feq(1.01, (0.02, 0.0, -0.01))
+    n = geo.coords.shape[1]
+    s.set_f(0, np.repeat((feq + fneq)[:, None], n, axis=1))
+    wss = s.wss()
+    y = geo.coords[1]
+    expect = (1 - 1 / (2 * tau)) * math.hypot(Pi[0, 1], Pi[2, 1])
+    edge = (y == 0) | (y == 3)
+    assert np.all(wss[~edge] == 0)
+    assert np.abs(wss[edge] - expect).max() < 1e-10 * expect
+
+
 @pytest.mark.parametrize("q", [0.1, 0.25])
 def test_bouzidi_second_order_vs_bounce_back_first_order(oracle_mod, q):
     """Walls a tenth or a quarter of a spacing from the outer nodes (the
@@ -525,6 +554,29 @@ def test_womersley_pipe(oracle_mod):
     assert max(errs) < 0.06, errs
 
 
+def test_time_dependent_force_momentum_budget(oracle_mod):
+    """A uniform force F(t) = F0 cos(w t) in a box periodic in every direction:
+    the state stays uniform, and each step adds exactly F(t) to the momentum
+    (the first moment of Guo's source term together with the half-force shift
+    of the velocity the collision relaxes to).  So after n steps
+    j = F0 sum_{k<n} cos(w k), and the velocity read at step n is
+    (j + F(n)/2) / rho with rho = rho0: a force taken at the wrong step or with
+    the wrong phase breaks the sum."""
+    geo = synth.box(3, 2, 2)
+    F0 = np.array([2e-5, -1e-5, 3e-5])
+    omega = 0.37
+    s = _system(oracle_mod, geo, tau=0.9, F=tuple(F0), omega=omega)
+    for n in (1, 2, 7, 40):
+        s.step(n - s.t)
+        rho, u = s.moments()
+        assert np.abs(rho - 1.0).max() < 1e-14
+        j = F0 * sum(math.cos(omega * k) for k in range(n))
+        expect = j + 0.5 * F0 * math.cos(omega * n)
+        # the populations are O(1/10): round-off adds ~1e-17 to j per step;
+        # a force one step off changes j by F0 (1 - cos w) ~ 1e-6 at once
+        assert np.abs(u * rho - expect[:, None]).max() < 1e-15
+
+
 # --------------------------------------------------------------------------
 # Eq. (2) and the printed 1:3 example
 # --------------------------------------------------------------------------
@@ -629,6 +681,33 @@ def test_reverse_rule_sets_the_pressure_drop(oracle_mod):
     p6, _, _ = _coupled_halves(oracle_mod, 0.6)
     assert p0 > 0
     assert abs(p6 / p0 - 1.75) < 0.03 * 1.75, p6 / p0
+
+
+@pytest.mark.parametrize("mode", ["alternate", "both"])
+def test_exchange_directions_per_step(oracle_mod, mode):
+    """Sec. 3 has the coupling exchange alternate between its two directions:
+    in that mode the venous inlet velocities (forward rule) and the arterial
+    outlet density (reverse rule) that a step uses never change at the same
+    step, and once flow crosses the coupling exactly one of them changes at
+    every step, taking turns.  Exchanging both ways every step changes both."""
+    m = oracle_mod.ALTERNATE if mode == "alternate" else oracle_mod.BOTH
+    s, _, _ = _coupled_1to3(oracle_mod, m, 0)
+    prev_in, prev_out = s.last_bc(1)[:3].copy(), s.last_bc(0)[1]
+    fwd, rev = [], []
+    for _ in range(160):
+        s.step(1)
+        b_in, b_out = s.last_bc(1)[:3], s.last_bc(0)[1]
+        fwd.append(bool(np.any(b_in != prev_in)))
+        rev.append(bool(b_out != prev_out))
+        prev_in, prev_out = b_in.copy(), b_out
+    fwd, rev = np.array(fwd), np.array(rev)
+    late = slice(100, None)
+    if mode == "alternate":
+        assert not np.any(fwd & rev)
+        assert np.all(fwd[late] ^ rev[late])
+        assert np.all(fwd[late][1:] != fwd[late][:-1])
+    else:
+        assert np.all(fwd[late] & rev[late])
 
 
 def _coupled_1to3_pulsatile(oracle_mod, mode, steps):
