@@ -304,7 +304,10 @@ int hl_commit(hl_ctx *ctx);
  * steps with initialisation and output excluded).  Asynchronous on the
  * context stream.  HL_E_INVAL for nsteps < 0; HL_E_DIVERGED when an earlier
  * step produced a non-finite density (sticky until hl_set_state or
- * hl_set_populations). */
+ * hl_set_populations); HL_E_DEVICE when a launch fails, after which part of
+ * the batch may already be queued and the step counter no longer matches the
+ * lattice: the only calls that remain meaningful are hl_last_error and
+ * hl_destroy. */
 int hl_step(hl_ctx *ctx, int64_t nsteps);
 
 /* Wait for the context stream; HL_E_DIVERGED as above.  Infrastructure (no
