@@ -155,6 +155,42 @@ MUTANTS = [
      "v[i] = (A0 / A[i]) * ratio / sum;",
      "v[i] = ratio / sum;",
      ["test_velocity_factors_conserve_mass"]),
+    ("iolet means: a site counted once per link to the iolet, not once",
+     "if (!seen) ks[nk++] = k;\n        }\n        for (int m = 0; m < nk; ++m) {\n            int k = ks[m];",
+     "ks[nk++] = k; (void)seen;\n        }\n        for (int m = 0; m < nk; ++m) {\n            int k = ks[m];",
+     ["test_iolet_means_are_site_averages"]),
+    ("iolet means: velocity taken along the opposite normal",
+     "for (int a = 0; a < 3; ++a) un = un + d->u[(size_t)a * d->n + x] * d->io[k].nrm[a];",
+     "for (int a = 0; a < 3; ++a) un = un - d->u[(size_t)a * d->n + x] * d->io[k].nrm[a];",
+     ["test_iolet_means_are_site_averages", "test_coupled_1to3_reaches_eq2_ratios"]),
+    ("moments: rest population left out of the density",
+     "        r = r + f[i];\n",
+     "        r = r + (i ? f[i] : 0.0);\n",
+     ["test_collision_conserves_and_relaxes", "test_mass_conserved_in_closed_domains"]),
+    ("streaming: rest population not collided",
+     "d->fn[x] = d->fs[x]; /* rest population stays */",
+     "d->fn[x] = d->f[x]; /* rest population stays */",
+     ["test_mass_conserved_in_closed_domains", "test_sparse_addressing_matches_dense_bruteforce"]),
+    ("bouzidi far branch: weight 1 - 1/q",
+     "v = fsi / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * d->fs[(size_t)ib * n + x];",
+     "v = fsi / (2.0 * q) + (1.0 - 1.0 / q) * d->fs[(size_t)ib * n + x];",
+     ["test_bouzidi_at_half_is_bounce_back", "test_bouzidi_far_wall_second_order"]),
+    ("bouzidi near branch: second node's population of the opposite direction",
+     "if (back >= 0) v = 2.0 * q * fsi + (1.0 - 2.0 * q) * d->fs[(size_t)i * n + back];",
+     "if (back >= 0) v = 2.0 * q * fsi + (1.0 - 2.0 * q) * d->fs[(size_t)ib * n + back];",
+     ["test_bouzidi_second_order_vs_bounce_back_first_order"]),
+    ("inlet profile: not clamped at zero beyond the radius",
+     "return v > 0.0 ? v : 0.0;",
+     "return v;",
+     ["test_open_domain_mass_budget"]),
+    ("inlet: Ladd term at the site's density instead of rho0",
+     "d->fn[(size_t)ib * n + x] = fsi - 6.0 * W[i] * RHO0 * cu;",
+     "d->fn[(size_t)ib * n + x] = fsi - 6.0 * W[i] * d->rho[x] * cu;",
+     ["test_open_domain_mass_budget"]),
+    ("coupling forward rule: profile factor summed over the inlet, not averaged",
+     "io->phibar = cnt[j] ? sp[j] / (double)cnt[j] : 0.0;",
+     "io->phibar = cnt[j] ? sp[j] : 0.0;",
+     ["test_coupled_1to3_reaches_eq2_ratios"]),
 ]
 
 
