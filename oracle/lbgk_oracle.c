@@ -52,8 +52,10 @@
  * printed number fixes; the tests pin what follows from it (flux
  * conservation, settling to the Eq. (2) ratios, and the steady pressure drop
  * of two coupled tubes scaling with 1/(1 - dP/P0) as Eq. (1) requires).
- * Parity unpinned: the velocity-reverse mode (VEL), held only to its rest
- * state and its instability.
+ * The velocity-reverse mode (VEL), another reading that runs away as read,
+ * is pinned in the early part of a run: the outlet value it sets, recomputed
+ * from the per-site moments and the geometry, and the mass budget of its
+ * velocity-driven outlet.
  *
  * Sums run over directions in index order and over sites in caller order.
  * Build with -ffp-contract=off so every product and sum is rounded as written.

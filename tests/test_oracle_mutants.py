@@ -191,6 +191,19 @@ MUTANTS = [
      "io->phibar = cnt[j] ? sp[j] / (double)cnt[j] : 0.0;",
      "io->phibar = cnt[j] ? sp[j] : 0.0;",
      ["test_coupled_1to3_reaches_eq2_ratios"]),
+    ("velocity reverse: vein mean multiplied by s instead of divided",
+     "sum = sum + s->d[o->db].io[o->kb].mean_u / o->s;",
+     "sum = sum + s->d[o->db].io[o->kb].mean_u * o->s;",
+     ["test_velocity_reverse_rule_from_outside"]),
+    ("velocity reverse: mean imposed as the peak",
+     "out->held = out->phibar > 0.0 ? (sum / (double)cnt) / out->phibar : 0.0;",
+     "out->held = out->phibar > 0.0 ? (sum / (double)cnt) : 0.0;",
+     ["test_velocity_reverse_rule_from_outside"]),
+    ("velocity reverse: outlet driven along its inward normal",
+     "for (int a = 0; a < 3; ++a) cu = cu + C[i][a] * (io->bc * phi * io->nrm[a]);",
+     "for (int a = 0; a < 3; ++a) cu = cu + C[i][a] * (io->bc * phi * io->nrm[a])"
+     " * (io->kind == KIND_OUTLET ? -1.0 : 1.0);",
+     ["test_velocity_reverse_rule_from_outside"]),
 ]
 
 

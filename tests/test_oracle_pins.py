@@ -793,3 +793,55 @@ def test_velocity_reverse_reading_is_unstable(oracle_mod):
     ref, _, _ = _coupled_1to3(oracle_mod, oracle_mod.ALTERNATE, 100)
     _, u_ref = ref.moments(0)
     assert np.abs(u_ref).max() < 0.05
+
+
+def _bordering(geo, k):
+    """Sites with at least one link into iolet k."""
+    return np.any(geo.nbr[1:] == -2 - k, axis=0)
+
+
+def _profile(geo, io, sites):
+    d = geo.coords[:, sites].T - np.asarray(io.centre, float)
+    n = np.asarray(io.normal, float)
+    r2 = (d * d).sum(1) - (d @ n) ** 2
+    return np.maximum(0.0, 1.0 - r2 / io.radius ** 2)
+
+
+def test_velocity_reverse_rule_from_outside(oracle_mod):
+    """The velocity-reverse reading (R9's other reading), in the early part of
+    a run before it runs away, checked against quantities recomputed here from
+    the per-site moments and the geometry: (a) the peak velocity the arterial
+    outlet takes for the next step is the mean over its veins of (the vein's
+    inlet mean velocity along its normal) / s, divided by the outlet's mean
+    profile factor, so that the site mean of the imposed velocity is that mean;
+    (b) the mass one step moves through the artery equals what its two
+    velocity-driven iolets add link by link: minus 6 w_i rho0 (c_i . u_w) with
+    u_w along the inlet's inward and the outlet's outward normal."""
+    c, w = oracle_mod.lattice()
+    art = synth.tubes(1, radius=4.0, length=24)
+    ven = synth.tubes(3, radius=4.0, length=24)
+    s, s_fac, _ = _coupled_1to3(oracle_mod, oracle_mod.VEL | oracle_mod.BOTH, 40)
+    _, uv = s.moments(1)
+    mu = np.array([(uv[:, _bordering(ven, k)].T @ np.asarray(ven.iolets[k].normal, float)).mean()
+                   for k in range(3)])
+    out = art.iolets[1]
+    phibar = _profile(art, out, _bordering(art, 1)).mean()
+    expect = np.mean(mu / s_fac) / phibar
+    assert abs(expect) > 1e-5 and np.abs(uv).max() < 0.05    # flowing, still in the low-Mach range
+    m0 = _neumaier(s.f(0).ravel())
+    s.step(1)
+    bc = s.last_bc(0)
+    assert abs(bc[1] - expect) < 1e-12 * abs(expect)
+    m1 = _neumaier(s.f(0).ravel())
+    terms = []
+    for i in range(1, 19):
+        for k in (0, 1):
+            x = np.flatnonzero(art.nbr[i] == -2 - k)
+            if x.size == 0:
+                continue
+            io = art.iolets[k]
+            phi = _profile(art, io, x)
+            terms.extend(-6.0 * w[i] * 1.0 * (c[i] @ np.asarray(io.normal, float)) * bc[k] * phi)
+    budget = _neumaier(terms)
+    assert abs(budget) > 1e-6
+    assert abs((m1 - m0) - budget) < 1e-13 * art.coords.shape[1]

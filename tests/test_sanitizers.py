@@ -85,7 +85,7 @@ def test_layout_planner_under_sanitizers():
 
 PIN_SUBSET = ("rest_state or mass_budget or sparse_addressing or at_half or second_node or waveform or "
               "velocity_factors or reverse_reading or feq or collision or wall_shear or momentum_budget or "
-              "exchange_directions or state_injection")
+              "exchange_directions or state_injection or from_outside")
 
 
 def test_oracle_under_sanitizers():
