@@ -199,6 +199,40 @@ def test_open_domain_mass_budget(oracle_mod, narrow):
     assert abs((m1 - m0) - budget) < 1e-13 * n
 
 
+def test_plug_flow_is_a_fixed_point_of_the_open_boundaries(oracle_mod):
+    """A box periodic across a flow along z, open at both ends: a flat-profile
+    Ladd inlet at the bottom and an equilibrium outlet at rho0 at the top.  The
+    uniform equilibrium feq(rho0, U e_z) is then a fixed point of the whole
+    step, link by link: BGK leaves an equilibrium unchanged, the Ladd term
+    -6 w_i rho0 (c_i . u_w) is exactly feq_ib - feq_i of the imposed velocity
+    at rho0, and the outlet writes back the equilibrium at the site's own
+    velocity.  A slip in either rule (a sign, a factor, the wrong direction,
+    the wrong velocity) moves the state at the first step."""
+    from synth.geometry import INLET, OUTLET, Iolet, build_site_list
+    nx, ny, nz, U = 5, 4, 6, 0.02
+    gz, gy, gx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ez = np.array([0.0, 0.0, 1.0])
+    c_in = np.array([(nx - 1) / 2, (ny - 1) / 2, -0.5])
+    c_out = np.array([(nx - 1) / 2, (ny - 1) / 2, nz - 0.5])
+    geo = build_site_list(gx.ravel(), gy.ravel(), gz.ravel(), (nx, ny, nz), (True, True, False),
+                          [Iolet(INLET, c_in, ez, 6.0), Iolet(OUTLET, c_out, ez, 6.0)])
+    assert np.all(geo.nbr[1:] != -1)                  # no wall link anywhere
+    s = oracle_mod.System(1)
+    s.set_geometry(0, geo)
+    s.set_params(0, 0.8)
+    big = 1e7                                        # profile factor 1 - r^2/R^2 = 1 to 1e-13
+    s.set_iolet(0, 0, oracle_mod.INLET, c_in, ez, big, a0=U)
+    s.set_iolet(0, 1, oracle_mod.OUTLET, c_out, ez, big, a0=1.0)
+    s.init()
+    feq = oracle_mod.feq(1.0, (0.0, 0.0, U))
+    n = geo.coords.shape[1]
+    s.set_f(0, np.repeat(feq[:, None], n, axis=1))
+    s.step(20)
+    # round-off only (the deviation is ~1e-15 after 20 steps); a slip moves f by ~w U
+    assert np.abs(s.f() - feq[:, None]).max() < 1e-14
+    _, u = s.moments()
+    assert np.abs(u[2] - U).max() < 1e-14 and np.abs(u[:2]).max() < 1e-14
+
 def test_iolet_means_are_site_averages(oracle_mod):
     """The iolet means that feed the exchange and the readout are plain
     averages over the sites bordering each iolet: mean u.n with the iolet's
