@@ -41,7 +41,8 @@
 extern "C" {
 #endif
 
-/* status codes */
+/* status codes (every call that takes a context returns HL_E_INVAL when
+ * the context is NULL) */
 #define HL_OK 0
 #define HL_E_INVAL (-1)    /* malformed argument or inconsistent input */
 #define HL_E_RANGE (-2)    /* index or code out of range */

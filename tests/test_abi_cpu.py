@@ -120,6 +120,25 @@ def test_bad_arguments_rejected_before_device(hl):
     lib.hl_destroy(None)
 
 
+def test_every_context_call_rejects_a_null_context(hl):
+    """Each call of the header that takes a context returns HL_E_INVAL for a
+    NULL one (the other arguments NULL or 0), without a device."""
+    lib = hl.lib()
+    with open(HEADER) as fh:
+        names = re.findall(r"^int (hl_\w+)\(hl_ctx \*ctx", fh.read(), flags=re.M)
+    assert len(names) >= 30
+    bad = {}
+    for nm in names:
+        f = getattr(lib, nm)
+        args = [None]
+        for t in f.argtypes[1:]:
+            ptr = t in (ct.c_void_p, ct.c_char_p) or (isinstance(t, type) and issubclass(t, ct._Pointer))
+            args.append(None if ptr else 0)
+        rc = f(*args)
+        if rc != hl.HL_E_INVAL:
+            bad[nm] = rc
+    assert not bad, bad
+
 def test_copy_bandwidth_argument_checks(hl):
     """The copy-ceiling call rejects bad arguments on the host, before any
     device call (the pointers below are never touched)."""
