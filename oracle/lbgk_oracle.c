@@ -98,6 +98,9 @@ typedef struct {
     double period;
 } series_t;
 
+/* Boundary value of an uncoupled iolet at step t: a0 plus a truncated Fourier
+ * series of period T (the pulsatile inflow of the runs of Sec. 3; the
+ * coefficients are inputs).  Step 3 of the header. */
 static double series_at(const series_t *s, double t) {
     double v = s->a0;
     for (int m = 1; m <= s->nh; ++m) {
@@ -169,6 +172,8 @@ void or_lattice(int *c, double *w) {
     }
 }
 
+/* Second-order D3Q19 equilibrium (Qian, d'Humieres & Lallemand 1992) for the
+ * lattice of Sec. 2, first paragraph; c_s^2 = 1/3. */
 void or_feq(double rho, const double *u, double *feq) {
     init_weights();
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -178,7 +183,8 @@ void or_feq(double rho, const double *u, double *feq) {
     }
 }
 
-/* Moments of one site's populations: rho and u = (j + F/2)/rho. */
+/* Moments of one site's populations: rho and u = (j + F/2)/rho, the
+ * half-force shift of Guo, Zheng & Shi (2002). */
 void or_moments_site(const double *f, const double *F, double *rho, double *u) {
     double r = 0.0, j[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < Q; ++i) {
@@ -189,7 +195,8 @@ void or_moments_site(const double *f, const double *F, double *rho, double *u) {
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * F[a]) / r;
 }
 
-/* LBGK collision with Guo forcing for one site. */
+/* LBGK collision (the single relaxation time of Sec. 2) with Guo forcing
+ * (named in Sec. 3) for one site.  Step 4 of the header. */
 void or_collide_site(const double *f, const double *F, double tau, double *fstar) {
     init_weights();
     double rho, u[3], feq[Q];
@@ -204,7 +211,9 @@ void or_collide_site(const double *f, const double *F, double tau, double *fstar
     }
 }
 
-/* Inlet profile factor max(0, 1 - r^2/R^2), r = distance from the axis. */
+/* Inlet profile factor max(0, 1 - r^2/R^2), r = distance from the axis: the
+ * parabolic velocity profile of a velocity iolet (Sec. 2, velocity
+ * boundaries; R the iolet radius). */
 static double profile(const iolet_t *io, const int32_t *coords, int64_t n, int64_t x) {
     double d[3], dn = 0.0, dd = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -337,6 +346,8 @@ int or_couple(or_sys *s, int da, int ka, int db, int kb, double sv, double delta
 /* Coupling mode bits (COUPLE_BOTH, COUPLE_VEL); set before or_init. */
 void or_set_coupling_mode(or_sys *s, int mode) { s->mode = mode; }
 
+/* Body force of step t, F0 cos(omega t): the explicit Guo force of Sec. 3,
+ * here a uniform drive (omega = 0 for a steady one). */
 static void body_force(const domain_t *d, int64_t t, double *F) {
     double c = cos(d->omega * (double)t);
     for (int a = 0; a < 3; ++a) F[a] = d->F0[a] * c;
@@ -357,8 +368,9 @@ static void moments(domain_t *d, int64_t t, int nthreads) {
     }
 }
 
-/* Step 2: means over the sites that border each iolet.  One pass over the
- * sites in caller order; a site adds to every iolet it borders. */
+/* Step 2: means over the sites that border each iolet (Sec. 2.3: only
+ * averaged values cross a coupled boundary).  One pass over the sites in
+ * caller order; a site adds to every iolet it borders. */
 static void iolet_means(domain_t *d) {
     double *su = (double *)calloc((size_t)(d->n_iolet + 1), sizeof(double));
     double *sr = (double *)calloc((size_t)(d->n_iolet + 1), sizeof(double));
@@ -391,7 +403,9 @@ static void iolet_means(domain_t *d) {
     free(su); free(sr); free(cnt);
 }
 
-/* Step 3: boundary values for the stream that follows step t. */
+/* Step 3: boundary values for the stream that follows step t (Sec. 3: the
+ * coupled exchange with Eq. (1)-(2), alternating direction; series values
+ * for the other iolets). */
 static void boundary_values(or_sys *s) {
     int fwd = (s->mode & COUPLE_BOTH) || (s->t % 2 == 0);
     int rev = (s->mode & COUPLE_BOTH) || (s->t % 2 == 1);
@@ -440,7 +454,9 @@ static void boundary_values(or_sys *s) {
     }
 }
 
-/* Steps 4-5 for one domain: collide into fs, push-stream into fn. */
+/* Steps 4-5 for one domain: collide into fs, push-stream into fn (the D3Q19
+ * stream of Sec. 2 with rigid walls, halfway or Bouzidi-Firdaouss-Lallemand
+ * 2001, Ladd velocity and equilibrium pressure links). */
 static void collide_stream(domain_t *d, int64_t t, int nthreads) {
     double F[3];
     body_force(d, t, F);
@@ -555,6 +571,8 @@ int or_set_held(or_sys *s, int dom, int k, double v) {
     return 0;
 }
 
+/* nsteps lattice updates, each taking steps 1-6 of the header in order for
+ * every domain (Sec. 2.2 counts these as the update steps). */
 int or_step(or_sys *s, int64_t nsteps, int nthreads) {
     if (!s->ready) return -3;
     if (nthreads < 1) nthreads = 1;
@@ -615,7 +633,8 @@ int or_read_iolet_stats(or_sys *s, int dom, double *mean_u, double *mean_p, int6
     return 0;
 }
 
-/* Wall shear stress at every site with at least one wall link (0 elsewhere):
+/* Wall shear stress (the quantity Sec. 1 names as what 3D flow resolves along
+ * artery walls) at every site with at least one wall link (0 elsewhere):
  * sigma = -(1 - 1/(2 tau)) sum_i (f_i - feq_i) c_i c_i, traction t = sigma n,
  * wss = |t - (t.n) n|; n is the caller's normal or the normalised
  * -sum of the wall-link directions. */
